@@ -1,0 +1,291 @@
+"""Pins of the CPU oracle against what the mathematics fixes, independent of the oracle's own code.
+
+Each check uses something other than the oracle: a library routine for a special
+case (dense LAPACK Cholesky / solve, banded LAPACK), a closed form, exact integer
+arithmetic, high-precision arithmetic (mpmath), or finite differences.  The
+inputs use non-symmetric coupling blocks so that a transposed operand fails.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from paper_2509_03015_amd import inputs
+from tests.dense import dense, flat, relerr, sym_lower
+
+SIZES = [(1, 1), (1, 4), (2, 3), (3, 1), (3, 2), (4, 5), (5, 3), (7, 2), (8, 4), (9, 3), (16, 2),
+         (17, 3), (33, 1)]
+
+
+@pytest.mark.parametrize("N,n", SIZES)
+def test_factor_is_the_dense_cholesky_factor(N, n):
+    """Ld, Ls are exactly the blocks of LAPACK's Cholesky factor of the dense A (eq. (1))."""
+    Ad, As, _, _ = inputs.gen_dd(N, n, 1, seed=N * 31 + n)
+    L = np.linalg.cholesky(dense(Ad, As))
+    Ld, Ls = oracle.factor(Ad, As)
+    for i in range(N):
+        np.testing.assert_allclose(Ld[i], L[i * n:(i + 1) * n, i * n:(i + 1) * n], rtol=0, atol=1e-13)
+    for i in range(N - 1):
+        np.testing.assert_allclose(Ls[i], L[(i + 1) * n:(i + 2) * n, i * n:(i + 1) * n], rtol=0,
+                                   atol=1e-13)
+    # upper triangles of the diagonal factors are exactly zero
+    for i in range(N):
+        assert np.all(np.triu(Ld[i], 1) == 0)
+
+
+@pytest.mark.parametrize("N,n", SIZES)
+@pytest.mark.parametrize("d", [1, 3])
+def test_solve_matches_dense_lapack(N, n, d):
+    Ad, As, _, _ = inputs.gen_dd(N, n, d, seed=7 + N + 13 * n)
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((N, n, d))
+    X = oracle.solve(Ad, As, B)
+    Xd = np.linalg.solve(dense(Ad, As), flat(B)).reshape(N, n, d)
+    assert relerr(X, Xd) < 1e-13
+
+
+def test_only_lower_triangle_of_diagonal_blocks_is_read():
+    Ad, As, _, B = inputs.gen_dd(6, 4, 2, seed=3)
+    junk = Ad.copy()
+    iu = np.triu_indices(4, 1)
+    for i in range(6):
+        junk[i][iu] = 1e3 * (i + 1)
+    np.testing.assert_array_equal(oracle.solve(Ad, As, B), oracle.solve(junk, As, B))
+
+
+@pytest.mark.slow
+def test_solve_matches_banded_lapack_at_size():
+    """LAPACK band Cholesky (bandwidth 2n-1) as an independent solver at a larger size."""
+    N, n, d = 1024, 16, 2
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=11)
+    u = 2 * n - 1
+    ab = np.zeros((u + 1, N * n))
+    S = sym_lower(Ad)
+    # lower band storage: ab[k, j] = A[j + k, j]
+    for i in range(N):
+        for c in range(n):
+            j = i * n + c
+            for r in range(c, n):
+                ab[r - c, j] = S[i, r, c]
+            if i + 1 < N:
+                for r in range(n):
+                    ab[n - c + r, j] = As[i, r, c]
+    Xb = sla.solveh_banded(ab, flat(B), lower=True).reshape(N, n, d)
+    assert relerr(oracle.solve(Ad, As, B), Xb) < 1e-13
+
+
+def test_scalar_tridiagonal_closed_form():
+    """n = 1, A = tridiag(-1, 2, -1): (A^-1)_ij = min(i,j) (N+1-max(i,j)) / (N+1), 1-based."""
+    N, d = 200, 3
+    Ad = np.full((N, 1, 1), 2.0)
+    As = np.full((N - 1, 1, 1), -1.0)
+    B = np.random.default_rng(0).standard_normal((N, 1, d))
+    i = np.arange(1, N + 1)
+    Tinv = np.minimum.outer(i, i) * (N + 1 - np.maximum.outer(i, i)) / (N + 1)
+    X = oracle.solve(Ad, As, B)
+    assert relerr(X, (Tinv @ flat(B)).reshape(N, 1, d)) < 1e-12
+
+
+def test_kronecker_closed_form():
+    """A = T (x) M with T = tridiag(b, a, b): eigenpairs of T in closed form (DST-I basis)."""
+    N, n, d, a, b = 300, 4, 2, 3.0, 1.0
+    rng = np.random.default_rng(1)
+    G = rng.standard_normal((n, n))
+    M = G @ G.T / n + np.eye(n)
+    Ad = np.broadcast_to(a * M, (N, n, n)).copy()
+    As = np.broadcast_to(b * M, (N - 1, n, n)).copy()
+    B = rng.standard_normal((N, n, d))
+    k = np.arange(1, N + 1)
+    lam = a + 2 * b * np.cos(k * np.pi / (N + 1))
+    V = np.sqrt(2.0 / (N + 1)) * np.sin(np.outer(k, k) * np.pi / (N + 1))
+    Tinv = (V / lam[None, :]) @ V.T
+    Xc = np.einsum("ij,ab,jbc->iac", Tinv, np.linalg.inv(M), B)
+    assert relerr(oracle.solve(Ad, As, B), Xc) < 1e-12
+
+
+def test_block_diagonal_decouples():
+    """As = 0: each block solves on its own."""
+    Ad, _, _, B = inputs.gen_dd(5, 6, 2, seed=2)
+    As = np.zeros((4, 6, 6))
+    X = oracle.solve(Ad, As, B)
+    for i in range(5):
+        np.testing.assert_allclose(X[i], np.linalg.solve(sym_lower(Ad[i:i + 1])[0], B[i]), rtol=1e-13,
+                                   atol=1e-14)
+
+
+def test_two_block_explicit_formula():
+    """N = 2: X_1 from the Schur complement of A_00, then X_0 by back substitution."""
+    Ad, As, _, B = inputs.gen_dd(2, 5, 3, seed=9)
+    A00, A11, A10 = Ad[0], Ad[1], As[0]
+    S = A11 - A10 @ np.linalg.solve(A00, A10.T)
+    x1 = np.linalg.solve(S, B[1] - A10 @ np.linalg.solve(A00, B[0]))
+    x0 = np.linalg.solve(A00, B[0] - A10.T @ x1)
+    X = oracle.solve(Ad, As, B)
+    assert relerr(X, np.stack([x0, x1])) < 1e-14
+
+
+def test_manufactured_solution_configs0():
+    """N=64, n=16, d=1, diagonally dominant: X recovered to about kappa * u."""
+    Ad, As, Xt, B = inputs.gen_dd(64, 16, 1, seed=0)
+    assert relerr(oracle.solve(Ad, As, B), Xt) < 1e-14
+
+
+def test_matvec_matches_dense():
+    Ad, As, X, _ = inputs.gen_dd(7, 3, 2, seed=4)
+    np.testing.assert_allclose(flat(oracle.matvec(Ad, As, X)), dense(Ad, As) @ flat(X), rtol=1e-14,
+                               atol=1e-13)
+
+
+def test_reconstruction_LLt():
+    Ad, As, _, _ = inputs.gen_dd(9, 4, 1, seed=6)
+    Ld, Ls = oracle.factor(Ad, As)
+    N, n = 9, 4
+    L = np.zeros((N * n, N * n))
+    for i in range(N):
+        L[i * n:(i + 1) * n, i * n:(i + 1) * n] = Ld[i]
+    for i in range(N - 1):
+        L[(i + 1) * n:(i + 2) * n, i * n:(i + 1) * n] = Ls[i]
+    A = dense(Ad, As)
+    assert np.linalg.norm(L @ L.T - A) / np.linalg.norm(A) < 1e-15 * N * n
+
+
+def test_logdet_matches_slogdet():
+    Ad, As, _, _ = inputs.gen_dd(12, 5, 1, seed=8)
+    Ld, _ = oracle.factor(Ad, As)
+    sign, ref = np.linalg.slogdet(dense(Ad, As))
+    assert sign == 1.0
+    assert abs(oracle.logdet(Ld) - ref) < 1e-12 * abs(ref)
+
+
+def test_not_spd_detected_at_natural_order_block():
+    Ad, As, _, _ = inputs.gen_dd(10, 4, 1, seed=1)
+    bad = Ad.copy()
+    bad[5, 2, 2] = -50.0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.factor(bad, As)
+    assert e.value.block == 5 and e.value.column == 2
+    nan = Ad.copy()
+    nan[3, 0, 0] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.factor(nan, As)
+    assert e.value.block == 3 and e.value.column == 0
+
+
+def _grad_by_central_differences(Ad, As, B, W, h=1e-6):
+    """Finite differences of sum(W * A^-1 B) with LAPACK dense solves (independent of the oracle)."""
+    N, n, _ = Ad.shape
+
+    def loss(ad, as_):
+        return float(np.sum(flat(W) * np.linalg.solve(dense(ad, as_), flat(B))))
+
+    gd = np.zeros_like(Ad)
+    for i in range(N):
+        for r in range(n):
+            for c in range(r + 1):
+                # symmetric direction e_r e_c^T + e_c e_r^T (one stored lower entry)
+                p, m = Ad.copy(), Ad.copy()
+                p[i, r, c] += h
+                m[i, r, c] -= h
+                if r != c:
+                    p[i, c, r] += h
+                    m[i, c, r] -= h
+                g = (loss(p, As) - loss(m, As)) / (2 * h)
+                # <dAd, E> = dAd[r,c] + dAd[c,r] = 2 dAd[r,c] for r != c (dAd symmetric)
+                gd[i, r, c] = g if r == c else g / 2
+                gd[i, c, r] = gd[i, r, c]
+    gs = np.zeros_like(As)
+    for i in range(N - 1):
+        for r in range(n):
+            for c in range(n):
+                p, m = As.copy(), As.copy()
+                p[i, r, c] += h
+                m[i, r, c] -= h
+                gs[i, r, c] = (loss(Ad, p) - loss(Ad, m)) / (2 * h)
+    gb = np.zeros_like(B)
+    for idx in np.ndindex(*B.shape):
+        p, m = B.copy(), B.copy()
+        p[idx] += h
+        m[idx] -= h
+        gb[idx] = (float(np.sum(flat(W) * np.linalg.solve(dense(Ad, As), flat(p))))
+                   - float(np.sum(flat(W) * np.linalg.solve(dense(Ad, As), flat(m))))) / (2 * h)
+    return gd, gs, gb
+
+
+def test_backward_matches_finite_differences():
+    N, n, d = 4, 3, 2
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=12)
+    W = np.random.default_rng(3).standard_normal((N, n, d))
+    X = oracle.solve(Ad, As, B)
+    dAd, dAs, dB = oracle.backward(Ad, As, X, W)
+    gd, gs, gb = _grad_by_central_differences(Ad, As, B, W)
+    np.testing.assert_allclose(dAd, gd, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(dAs, gs, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(dB, gb, rtol=0, atol=1e-7)
+
+
+def test_backward_matches_dense_inverse_gradient():
+    """dl/dA = -A^-1 W X^T on the dense matrix, restricted to the stored parameters."""
+    N, n, d = 6, 4, 3
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=13)
+    W = np.random.default_rng(4).standard_normal((N, n, d))
+    A = dense(Ad, As)
+    X = np.linalg.solve(A, flat(B))
+    Gd = -np.linalg.inv(A) @ flat(W) @ X.T
+    dAd, dAs, dB = oracle.backward(Ad, As, X.reshape(N, n, d), W)
+    for i in range(N):
+        blk = Gd[i * n:(i + 1) * n, i * n:(i + 1) * n]
+        np.testing.assert_allclose(dAd[i], 0.5 * (blk + blk.T), rtol=1e-12, atol=1e-13)
+    for i in range(N - 1):
+        below = Gd[(i + 1) * n:(i + 2) * n, i * n:(i + 1) * n]
+        above = Gd[i * n:(i + 1) * n, (i + 1) * n:(i + 2) * n]
+        np.testing.assert_allclose(dAs[i], below + above.T, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(flat(dB), np.linalg.solve(A, flat(W)), rtol=1e-12, atol=1e-13)
+
+
+def test_long_double_solve_is_more_accurate_on_exact_integer_system():
+    """tridiag(-1,2,-1), N=2000 (kappa ~ 1.6e6): integer X and B = A X exact in FP64."""
+    N = 2000
+    Ad = np.full((N, 1, 1), 2.0)
+    As = np.full((N - 1, 1, 1), -1.0)
+    Xt = np.random.default_rng(0).integers(-50, 50, size=(N, 1, 2)).astype(np.float64)
+    B = inputs.block_matvec(Ad, As, Xt)
+    assert np.all(B == np.round(B))
+    e_ld = relerr(oracle.solve_ld(Ad, As, B), Xt)
+    e_d = relerr(oracle.solve(Ad, As, B), Xt)
+    assert e_ld < 1e-15          # about the final rounding to FP64 (FP64 arithmetic gives ~1e-12)
+    assert e_d < 1e-9
+    assert e_d > 100 * e_ld
+
+
+def test_long_double_loss_matches_mpmath():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    N, n, d = 4, 2, 2
+    Ad, As, _, B = inputs.gen_kalman(N, n, d, rho=50.0, seed=2)
+    W = np.random.default_rng(1).standard_normal((N, n, d))
+    A = mp.matrix(dense(Ad, As).tolist())
+    ref = mp.mpf(0)
+    for j in range(d):
+        x = mp.lu_solve(A, mp.matrix([float(v) for v in flat(B)[:, j]]))
+        ref += mp.fsum(mp.mpf(float(w)) * x[i] for i, w in enumerate(flat(W)[:, j]))
+    hi, lo = oracle.loss_ld(Ad, As, B, W)
+    assert abs((mp.mpf(hi) + mp.mpf(lo)) - ref) <= mp.mpf("1e-17") * abs(ref)
+
+
+def test_batched_equals_single_system_calls():
+    systems = [inputs.gen_dd(N, n, d, seed=k)[0:2] + (inputs.gen_dd(N, n, d, seed=k)[3],)
+               for k, (N, n, d) in enumerate([(5, 3, 1), (1, 2, 2), (9, 4, 3), (2, 1, 1)])]
+    Xs, used = oracle.solve_batched(systems)
+    assert used >= 1
+    for (Ad, As, B), X in zip(systems, Xs):
+        np.testing.assert_array_equal(X, oracle.solve(Ad, As, B))
+
+
+def test_matvec_reads_only_lower_triangle():
+    Ad, As, X, _ = inputs.gen_dd(5, 4, 2, seed=14)
+    junk = Ad.copy()
+    iu = np.triu_indices(4, 1)
+    for i in range(5):
+        junk[i][iu] = -7.0 * (i + 2)
+    np.testing.assert_allclose(flat(oracle.matvec(junk, As, X)), dense(Ad, As) @ flat(X), rtol=1e-14,
+                               atol=1e-13)
