@@ -1,0 +1,247 @@
+// Device-side building blocks for gfx950: the MFMA wave-tile engine and the
+// per-block Cholesky + triangular-inverse routine.
+//
+// MFMA conventions (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32, wave64):
+// for lane l let i = l % 16 and g = l / 16.  One instruction multiplies a
+// 16 x 4 A fragment (lane l holds A[i][g]) by a 4 x 16 B fragment (lane l
+// holds B[g][j=i]) into a 16 x 16 accumulator where lane l holds rows
+// 4g .. 4g+3 of column i.  The engine walks K in chunks of 16 and feeds k-step
+// s of a chunk with k = 4g + s, so that each lane reads four consecutive k
+// (a vector load when the operand is contiguous along k); A and B use the same
+// order, so every product term is summed exactly once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bds.h"
+
+namespace bds {
+
+constexpr int kMaxNP = 256;  // largest padded block size
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct AccT;
+template <> struct AccT<double> { using type = dx4; };
+template <> struct AccT<float> { using type = fx4; };
+
+__device__ __forceinline__ dx4 mma(double a, double b, dx4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ fx4 mma(float a, float b, fx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+template <typename T, int RM, int RN>
+__device__ __forceinline__ void acc_zero(typename AccT<T>::type (&acc)[RM][RN])
+{
+#pragma unroll
+    for (int a = 0; a < RM; ++a)
+#pragma unroll
+        for (int b = 0; b < RN; ++b) acc[a][b] = typename AccT<T>::type{0, 0, 0, 0};
+}
+
+// Operand orientation.
+//   A (M x K): A_MK -> element (m,k) at A[m*lda + k];  otherwise at A[k*lda + m].
+//   B (K x N): B_NK -> element (k,n) at B[n*ldb + k];  otherwise at B[k*ldb + n].
+// B_MASK: columns n >= ncols of B read as zero (right-hand sides with d < 16).
+// acc[a][b] accumulates the 16 x 16 output tile (m0 + 16a, n0 + 16b).
+// k0, k1: multiples of 16.
+template <typename T, int RM, int RN, bool A_MK, bool B_NK, bool B_MASK = false, typename SA,
+          typename SB>
+__device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], const SA* A,
+                                         int64_t lda, const SB* B, int64_t ldb, int m0, int n0,
+                                         int k0, int k1, int ncols = 1 << 30)
+{
+    const int l = lane_id();
+    const int i = l & 15, g = l >> 4;
+    for (int kc = k0; kc < k1; kc += 16) {
+        const int k = kc + 4 * g;
+        T a[RM][4], b[RN][4];
+#pragma unroll
+        for (int ta = 0; ta < RM; ++ta) {
+            const int m = m0 + 16 * ta + i;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                a[ta][s] = A_MK ? (T)A[(int64_t)m * lda + k + s] : (T)A[(int64_t)(k + s) * lda + m];
+        }
+#pragma unroll
+        for (int tb = 0; tb < RN; ++tb) {
+            const int n = n0 + 16 * tb + i;
+            const bool ok = !B_MASK || n < ncols;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                b[tb][s] = ok ? (B_NK ? (T)B[(int64_t)n * ldb + k + s] : (T)B[(int64_t)(k + s) * ldb + n])
+                              : (T)0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int ta = 0; ta < RM; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < RN; ++tb) acc[ta][tb] = mma(a[ta][s], b[tb][s], acc[ta][tb]);
+    }
+}
+
+// Visit every element of a wave's accumulator tile: f(row, col, value).
+template <typename T, int RM, int RN, typename F>
+__device__ __forceinline__ void acc_foreach(const typename AccT<T>::type (&acc)[RM][RN], int m0,
+                                            int n0, F f)
+{
+    const int l = lane_id();
+    const int i = l & 15, g = l >> 4;
+#pragma unroll
+    for (int ta = 0; ta < RM; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < RN; ++tb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) f(m0 + 16 * ta + 4 * g + r, n0 + 16 * tb + i, acc[ta][tb][r]);
+}
+
+__device__ __forceinline__ void report_notspd(bds_info* info, int level, int pos, int orig, int col)
+{
+    if (!info) return;
+    if (atomicCAS(&info->status, 0, (int)BDS_ENOTSPD) == 0) {
+        info->level = level;
+        info->position = pos;
+        info->orig_block = orig;
+        info->column = col;
+    }
+}
+
+// Shared memory of one work-group running diag_factor_wg.
+template <typename T> struct DiagSmem {
+    T d[16][17];       // diagonal tile being factorised
+    T inv[16][16];     // inverse of its Cholesky factor
+    T z[4][16][16];    // per-wave staging tile
+    int bad_col;
+};
+
+// Cholesky factor and its inverse for one np x np SPD block, computed by a
+// whole 256-thread work-group (4 waves):
+//   D  (np x np, element type In, lower triangle read, ld = np)
+//   Lo (np x np, T): receives the lower Cholesky factor L of D.  It may alias
+//      D only when In == T (each tile is read before it is overwritten).
+//   Li (np x np, T): receives L^-1 (lower, explicit zeros above).
+// Left-looking blocked Cholesky on 16 x 16 tiles: the tile column J is updated
+// with the finished columns (MFMA), its diagonal tile is factorised and
+// inverted on one wave, and the tiles below are multiplied by the transposed
+// inverse (MFMA).  Then L^-1 is built by tile diagonals:
+//   Li[I][J] = -Li[I][I] * sum_{K=J}^{I-1} L[I][K] Li[K][J].
+// Returns the first column whose pivot is not positive, or -1.
+template <typename T, typename In>
+__device__ int diag_factor_wg(const In* D, T* Lo, T* Li, int np, DiagSmem<T>& sm)
+{
+    using A = typename AccT<T>::type;
+    const int w = wave_id(), l = lane_id();
+    const int nt = np / 16;
+    if (threadIdx.x == 0) sm.bad_col = -1;
+    // Upper tiles of Li are zero.
+    for (int t = w; t < nt * nt; t += 4) {
+        const int I = t / nt, J = t % nt;
+        if (J > I)
+            for (int e = l; e < 256; e += 64) Li[(int64_t)(16 * I + e / 16) * np + 16 * J + e % 16] = (T)0;
+    }
+    __syncthreads();
+    for (int J = 0; J < nt; ++J) {
+        // (a) update tile column J with the finished columns 0..J-1
+        for (int I = J + w; I < nt; I += 4) {
+            A acc[1][1];
+            acc_zero<T, 1, 1>(acc);
+            if (J > 0)
+                wave_mma<T, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np, np, Lo + (int64_t)16 * J * np,
+                                              np, 0, 0, 0, 16 * J);
+            acc_foreach<T, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
+                const T a = (T)D[(int64_t)(16 * I + m) * np + 16 * J + n];
+                if (I == J)
+                    sm.d[m][n] = a - v;
+                else
+                    Lo[(int64_t)(16 * I + m) * np + 16 * J + n] = a - v;
+            });
+        }
+        __syncthreads();
+        // (b) factor and invert the diagonal tile on wave 0
+        if (w == 0) {
+            for (int k = 0; k < 16; ++k) {
+                const T piv = sm.d[k][k];
+                if (!(piv > (T)0) && l == 0 && sm.bad_col < 0) sm.bad_col = 16 * J + k;
+                const T lkk = sqrt(piv);
+                T lrk = (T)0;
+                if (l > k && l < 16) lrk = sm.d[l][k] / lkk;
+                wave_sync();
+                if (l > k && l < 16) sm.d[l][k] = lrk;
+                if (l == 0) sm.d[k][k] = lkk;
+                wave_sync();
+                // trailing update d[r][c] -= d[r][k] d[c][k], k < c <= r < 16
+                for (int e = l; e < 256; e += 64) {
+                    const int r = e / 16, c = e % 16;
+                    if (c > k && r >= c) sm.d[r][c] -= sm.d[r][k] * sm.d[c][k];
+                }
+                wave_sync();
+            }
+            // inverse by elimination on the identity: row k /= L[k][k]; row r -= L[r][k] row k
+            for (int e = l; e < 256; e += 64) sm.inv[e / 16][e % 16] = (e / 16 == e % 16) ? (T)1 : (T)0;
+            wave_sync();
+            for (int k = 0; k < 16; ++k) {
+                if (l <= k) sm.inv[k][l] = sm.inv[k][l] / sm.d[k][k];
+                wave_sync();
+                // rows r > k, columns c <= k: (15 - k) * (k + 1) <= 64 updates
+                const int cnt = (15 - k) * (k + 1);
+                if (l < cnt) {
+                    const int r = k + 1 + l / (k + 1), c = l % (k + 1);
+                    sm.inv[r][c] -= sm.d[r][k] * sm.inv[k][c];
+                }
+                wave_sync();
+            }
+            for (int e = l; e < 256; e += 64) {
+                const int r = e / 16, c = e % 16;
+                Lo[(int64_t)(16 * J + r) * np + 16 * J + c] = (c <= r) ? sm.d[r][c] : (T)0;
+                Li[(int64_t)(16 * J + r) * np + 16 * J + c] = sm.inv[r][c];
+            }
+        }
+        __syncthreads();
+        // (c) tiles below: L[I][J] = A[I][J] * inv^T
+        for (int I = J + 1 + w; I < nt; I += 4) {
+            A acc[1][1];
+            acc_zero<T, 1, 1>(acc);
+            wave_mma<T, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np + 16 * J, np, &sm.inv[0][0], 16,
+                                          0, 0, 0, 16);
+            acc_foreach<T, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
+                Lo[(int64_t)(16 * I + m) * np + 16 * J + n] = v;
+            });
+        }
+        __syncthreads();
+    }
+    // Li below the diagonal, one tile diagonal at a time
+    for (int dlt = 1; dlt < nt; ++dlt) {
+        for (int J = w; J + dlt < nt; J += 4) {
+            const int I = J + dlt;
+            A acc[1][1];
+            acc_zero<T, 1, 1>(acc);
+            wave_mma<T, 1, 1, true, false>(acc, Lo + (int64_t)16 * I * np, np, Li + 16 * J, np, 0, 0,
+                                           16 * J, 16 * I);
+            acc_foreach<T, 1, 1>(acc, 0, 0, [&](int m, int n, T v) { sm.z[w][m][n] = v; });
+            wave_sync();
+            A acc2[1][1];
+            acc_zero<T, 1, 1>(acc2);
+            wave_mma<T, 1, 1, true, false>(acc2, Li + (int64_t)16 * I * np + 16 * I, np, &sm.z[w][0][0], 16,
+                                           0, 0, 0, 16);
+            acc_foreach<T, 1, 1>(acc2, 0, 0, [&](int m, int n, T v) {
+                Li[(int64_t)(16 * I + m) * np + 16 * J + n] = -v;
+            });
+            wave_sync();
+        }
+        __syncthreads();
+    }
+    return sm.bad_col;
+}
+
+}  // namespace bds

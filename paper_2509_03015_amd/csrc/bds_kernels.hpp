@@ -1,0 +1,138 @@
+// Kernel argument records and launch entry points of libbds (host-visible).
+//
+// Every kernel reads its per-system arguments through a "table": either one
+// record passed by value (single system) or a device array of records with
+// an exclusive prefix sum of work units per record (batched systems, one
+// launch per level across the whole batch).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bds.h"
+
+namespace bds {
+
+// One reduction level of one system (factorisation).
+template <typename T, typename In> struct FacLv {
+    const In* Ad;   // M diagonal blocks of this level (np x np, lower triangle read)
+    const In* As;   // M-1 sub-diagonal blocks
+    T* Li;          // E interiors: inverse Cholesky factor
+    T* Wl;          // E interiors: Li * A[i,i-1]
+    T* Pr;          // E interiors: A[i+1,i] * Li^T
+    T* Adn;         // Mn next-level diagonal blocks
+    T* Asn;         // Mn-1 next-level sub-diagonal blocks
+    int M, np, level, pad;
+    bds_info* info;
+};
+
+// Coarse system of one system (sequential block Cholesky, FP64).
+template <typename In> struct CoarseFac {
+    const In* Ad;
+    const In* As;
+    double* Lc;     // Mc: inverse Cholesky factors of the pivots
+    double* Lsc;    // Mc-1: A[i+1,i] Lc[i]^T
+    double* Cw;     // 1 block scratch
+    int Mc, np, level, pad;
+    bds_info* info;
+};
+
+// One reduction level of one system (solve); vectors FP64, np x d blocks, ld d.
+template <typename T> struct SolLv {
+    const T* Li;
+    const T* Wl;
+    const T* Pr;
+    const double* B;   // M blocks: right-hand side of this level
+    double* Y;         // E blocks
+    double* Bn;        // Mn blocks
+    const double* Xn;  // Mn blocks
+    double* X;         // M blocks: solution of this level
+    int M, np, d, pad;
+};
+
+struct CoarseSol {
+    const double* Lc;
+    const double* Lsc;
+    const double* B;
+    double* Y;
+    double* X;
+    int Mc, np, d, pad;
+};
+
+// Refinement helpers: residual R = B - A X over the whole (padded) system.
+struct ResidArgs {
+    const double* Ad;  // N blocks np x np (ld np), lower triangle read
+    const double* As;  // N-1 blocks
+    const double* B;   // N blocks np x d
+    const double* X;
+    double* R;
+    int N, np, d, pad;
+};
+
+struct AxpyArgs {
+    double* X;          // N blocks np x d: X += C
+    const double* C;
+    double* part;       // 2 * N partial sums (sum C^2, sum X^2 per block)
+    double* out;        // 2 final sums
+    int N, np, d, pad;
+};
+
+struct AdjArgs {
+    const double* G;    // N blocks np x d (padded)
+    const double* X;    // N blocks np x d (padded)
+    double* dAd;        // N blocks n x n (ld n)
+    double* dAs;        // N-1 blocks n x n
+    int N, n, np, d;
+};
+
+// Work-unit counts per record (waves for wave kernels, work-groups otherwise).
+int64_t units_fac_diag(int M);
+int64_t units_fac_couple(int M, int np);
+int64_t units_fac_schur(int M, int np);
+int64_t units_sol_fwd_int(int M, int np, int d);
+int64_t units_sol_fwd_sep(int M, int np, int d);
+int64_t units_sol_bwd(int M, int np, int d);
+int64_t units_resid(int N, int np, int d);
+
+// Launchers.  tab_dev/start_dev == nullptr: single record passed by value.
+// Otherwise K records at tab_dev with exclusive prefix sums start_dev (K+1).
+template <typename T, typename In>
+hipError_t launch_factor_level(const FacLv<T, In>& one, const FacLv<T, In>* tab_dev,
+                               const int64_t* start_diag, const int64_t* start_couple,
+                               const int64_t* start_schur, int K, int64_t tot_diag,
+                               int64_t tot_couple, int64_t tot_schur, int np_max, hipStream_t st);
+
+template <typename In>
+hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab_dev, int K,
+                                hipStream_t st);
+
+template <typename T>
+hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab_dev, const int64_t* start_int,
+                            const int64_t* start_sep, int K, int64_t tot_int, int64_t tot_sep,
+                            int np_max, hipStream_t st);
+
+template <typename T>
+hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab_dev, const int64_t* start,
+                            int K, int64_t tot, int np_max, hipStream_t st);
+
+hipError_t launch_coarse_solve(const CoarseSol& one, const CoarseSol* tab_dev, const int64_t* start,
+                               int K, int64_t tot, hipStream_t st);
+
+hipError_t launch_residual(const ResidArgs& one, const ResidArgs* tab_dev, const int64_t* start, int K,
+                           int64_t tot, int np_max, hipStream_t st);
+
+hipError_t launch_axpy_norm(const AxpyArgs& one, const AxpyArgs* tab_dev, const int64_t* start, int K,
+                            int64_t tot, hipStream_t st);
+
+hipError_t launch_adjoint(const AdjArgs& a, hipStream_t st);
+
+hipError_t launch_pack_blocks(const double* src, double* dst, int64_t nblk, int n, int np, bool diag,
+                              hipStream_t st);
+hipError_t launch_pack_rhs(const double* src, double* dst, int64_t nblk, int n, int np, int d,
+                           hipStream_t st);
+hipError_t launch_unpack_rhs(const double* src, double* dst, int64_t nblk, int n, int np, int d,
+                             hipStream_t st);
+hipError_t launch_clear_info(bds_info* info, int K, hipStream_t st);
+hipError_t launch_set_refine_info(bds_info* info, int iters, int converged, hipStream_t st);
+
+}  // namespace bds

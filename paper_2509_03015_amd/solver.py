@@ -1,0 +1,176 @@
+"""Python API over libbds: tensors and streams from PyTorch, all arithmetic in the HIP library.
+
+    F = factor(Ad, As, prec="f64")      # recursive factorisation (the paper's Alg. 4)
+    X = F.solve(B)                      # recursive solve (Alg. 5-7), refined if prec != "f64"
+    X = solve(Ad, As, B)                # differentiable: torch.autograd.Function
+
+Shapes (float64, CUDA/HIP device, C-contiguous): Ad (N, n, n) with only the
+lower triangle read, As (N-1, n, n) with As[i] = A[i+1, i], B (N, n, d).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _binding as bb
+
+PRECISIONS = {"f64": bb.BDS_F64, "f32": bb.BDS_F32, "bf16": bb.BDS_BF16}
+
+
+class BdsError(RuntimeError):
+    def __init__(self, code: int, what: str, info: dict | None = None):
+        self.code = code
+        self.info = info
+        super().__init__(f"{what}: {bb.STATUS_NAMES.get(code, code)}" + (f" {info}" if info else ""))
+
+
+def _stream_handle(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(t: torch.Tensor, name: str, shape: tuple, device: torch.device | None = None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+def _info_dict(info: torch.Tensor) -> dict:
+    v = info.cpu().tolist()
+    keys = ("status", "level", "position", "orig_block", "column", "iters", "converged", "reserved")
+    return dict(zip(keys, v))
+
+
+class Factor:
+    """Factor hierarchy of one SPD block-tridiagonal matrix, held in a device workspace."""
+
+    def __init__(self, Ad: torch.Tensor, As: torch.Tensor | None, prec: str = "f64", nstar: int = 0,
+                 check: bool = True):
+        if Ad.dim() != 3:
+            raise ValueError("Ad must have shape (N, n, n)")
+        N, n, _ = Ad.shape
+        self.device = Ad.device
+        _check_tensor(Ad, "Ad", (N, n, n))
+        if N > 1:
+            _check_tensor(As, "As", (N - 1, n, n), self.device)
+        self.N, self.n = int(N), int(n)
+        self.prec = prec
+        self.nstar = int(nstar)
+        self.Ad, self.As = Ad, (As if N > 1 else None)
+        self._solve_ws = {}
+        desc = self._desc(1)
+        rc, fbytes, _ = bb.workspace_size(desc)
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_workspace_size")
+        self.fbytes = fbytes
+        self.fws = torch.empty(max(fbytes, 1), dtype=torch.uint8, device=self.device)
+        self.info_t = torch.zeros(8, dtype=torch.int32, device=self.device)
+        rc = bb.load().bds_factor(ctypes.byref(desc), _ptr(Ad), _ptr(self.As), _ptr(self.fws), fbytes,
+                                  _ptr(self.info_t), _stream_handle(self.device))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_factor")
+        if check:
+            self.check("bds_factor")
+
+    def _desc(self, d: int, max_refine: int = 0, refine_tol: float = 0.0) -> bb.BdsDesc:
+        if self.prec not in PRECISIONS:
+            raise ValueError(f"prec must be one of {list(PRECISIONS)}")
+        return bb.BdsDesc(self.N, self.n, int(d), PRECISIONS[self.prec], self.nstar, int(max_refine), 0,
+                          float(refine_tol))
+
+    def info(self) -> dict:
+        """Synchronise and read the device info record of the last call."""
+        return _info_dict(self.info_t)
+
+    def check(self, what: str = "bds"):
+        inf = self.info()
+        if inf["status"] != bb.BDS_OK:
+            raise BdsError(inf["status"], what, inf)
+        return inf
+
+    def _workspace(self, d: int, desc: bb.BdsDesc):
+        ws = self._solve_ws.get(d)
+        if ws is None:
+            rc, _, sbytes = bb.workspace_size(desc)
+            if rc != bb.BDS_OK:
+                raise BdsError(rc, "bds_workspace_size")
+            ws = torch.empty(max(sbytes, 1), dtype=torch.uint8, device=self.device)
+            self._solve_ws[d] = ws
+        return ws
+
+    def solve(self, B: torch.Tensor, out: torch.Tensor | None = None, max_refine: int = 0,
+              refine_tol: float = 0.0, check: bool = True) -> torch.Tensor:
+        if B.dim() != 3:
+            raise ValueError("B must have shape (N, n, d)")
+        d = int(B.shape[2])
+        _check_tensor(B, "B", (self.N, self.n, d), self.device)
+        X = torch.empty_like(B) if out is None else out
+        _check_tensor(X, "out", (self.N, self.n, d), self.device)
+        desc = self._desc(d, max_refine, refine_tol)
+        ws = self._workspace(d, desc)
+        rc = bb.load().bds_solve(ctypes.byref(desc), _ptr(self.fws), self.fbytes, _ptr(self.Ad), _ptr(self.As),
+                                 _ptr(B), _ptr(X), _ptr(ws), ws.numel(), _ptr(self.info_t),
+                                 _stream_handle(self.device))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_solve")
+        if check and self.prec != "f64":
+            self.check("bds_solve")
+        return X
+
+    def backward(self, X: torch.Tensor, dX: torch.Tensor, check: bool = True):
+        """Gradients (dAd, dAs, dB) of a loss with dL/dX = dX, for X = A^-1 B."""
+        d = int(X.shape[2])
+        _check_tensor(X, "X", (self.N, self.n, d), self.device)
+        _check_tensor(dX, "dX", (self.N, self.n, d), self.device)
+        desc = self._desc(d)
+        ws = self._workspace(d, desc)
+        dAd = torch.empty((self.N, self.n, self.n), dtype=torch.float64, device=self.device)
+        dAs = torch.empty((max(self.N - 1, 0), self.n, self.n), dtype=torch.float64, device=self.device)
+        dB = torch.empty_like(X)
+        rc = bb.load().bds_backward(ctypes.byref(desc), _ptr(self.fws), self.fbytes, _ptr(self.Ad), _ptr(self.As),
+                                    _ptr(X), _ptr(dX), _ptr(dAd), _ptr(dAs), _ptr(dB), _ptr(ws), ws.numel(),
+                                    _ptr(self.info_t), _stream_handle(self.device))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_backward")
+        if check and self.prec != "f64":
+            self.check("bds_backward")
+        return dAd, dAs, dB
+
+
+def factor(Ad: torch.Tensor, As: torch.Tensor | None, prec: str = "f64", nstar: int = 0,
+           check: bool = True) -> Factor:
+    return Factor(Ad, As, prec=prec, nstar=nstar, check=check)
+
+
+class _Solve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Ad, As, B, prec, nstar):
+        F = Factor(Ad.detach(), As.detach() if As is not None else None, prec=prec, nstar=nstar)
+        X = F.solve(B.detach())
+        ctx.F = F
+        ctx.save_for_backward(X)
+        return X
+
+    @staticmethod
+    def backward(ctx, dX):
+        (X,) = ctx.saved_tensors
+        dAd, dAs, dB = ctx.F.backward(X, dX.contiguous())
+        return dAd, dAs, dB, None, None
+
+
+def solve(Ad: torch.Tensor, As: torch.Tensor, B: torch.Tensor, prec: str = "f64", nstar: int = 0) -> torch.Tensor:
+    """X = A^-1 B, differentiable in Ad (as a symmetric block), As and B."""
+    return _Solve.apply(Ad, As, B, prec, nstar)

@@ -1,0 +1,96 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes workspaces on the host, and rejects bad arguments
+before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2509_03015_amd import _binding as bb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "bds.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(bds_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(bb.LIB_PATH):
+        from paper_2509_03015_amd import build
+        build.build()
+    return bb.load()
+
+
+def test_header_declares_the_entry_points():
+    fns = header_functions()
+    for f in ("bds_factor", "bds_solve", "bds_factor_batched", "bds_solve_batched", "bds_backward",
+              "bds_workspace_size", "bds_batched_workspace_size"):
+        assert f in fns
+    assert set(fns) == set(bb.EXPORTS)
+
+
+def test_library_exports_every_header_symbol(lib):
+    for f in header_functions():
+        assert hasattr(lib, f), f
+    assert b"gfx950" in lib.bds_version()
+
+
+def desc(N=64, n=16, d=1, prec=0, nstar=0, max_refine=0, reserved=0, tol=0.0):
+    return bb.BdsDesc(N, n, d, prec, nstar, max_refine, reserved, tol)
+
+
+def test_workspace_sizes_follow_the_level_plan(lib):
+    rc, f, s = bb.workspace_size(desc(64, 16, 1))
+    assert rc == 0
+    # levels M = 64, 32, 16, 8, 4, 2 (nstar = 1): interiors 32+16+8+4+2+1 = 63
+    blk = 16 * 16 * 8
+    interiors = 63
+    nxt_d = 32 + 16 + 8 + 4 + 2 + 1
+    nxt_s = 31 + 15 + 7 + 3 + 1 + 0
+    lower = (3 * interiors + nxt_d + nxt_s) * blk + (1 + 0 + 1) * blk
+    assert lower <= f <= lower + 256 * 40
+    rc2, f2, s2 = bb.workspace_size(desc(64, 16, 7))
+    assert rc2 == 0 and f2 == f and s2 > s
+    rc3, f3, _ = bb.workspace_size(desc(64, 16, 1, prec=1))
+    assert rc3 == 0 and f3 < f            # FP32 levels, FP64 coarse
+    rc4, f4, _ = bb.workspace_size(desc(64, 16, 1, nstar=64))
+    assert rc4 == 0 and f4 < f            # no reduction level at all
+
+
+def test_padding_to_multiple_of_16(lib):
+    _, f17, _ = bb.workspace_size(desc(10, 17, 1))
+    _, f32, _ = bb.workspace_size(desc(10, 32, 1))
+    assert f17 > f32                      # same padded blocks plus the padded input copies
+
+
+@pytest.mark.parametrize("bad", [dict(N=0), dict(n=0), dict(n=257), dict(d=0), dict(prec=7), dict(nstar=-1),
+                                 dict(max_refine=-2), dict(reserved=1), dict(tol=-1.0)])
+def test_invalid_descriptors_rejected(lib, bad):
+    kw = dict(N=8, n=4, d=1)
+    kw.update(bad)
+    rc, _, _ = bb.workspace_size(desc(**kw))
+    assert rc == bb.BDS_EINVAL
+
+
+def test_calls_reject_bad_arguments_without_launching(lib):
+    d = desc(8, 4, 1)
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.bds_factor(ctypes.byref(d), null, null, fake, 1 << 20, fake, null) == bb.BDS_EINVAL
+    assert lib.bds_factor(ctypes.byref(d), fake, fake, fake, 16, fake, null) == bb.BDS_EWORKSPACE
+    assert lib.bds_solve(ctypes.byref(d), fake, 1 << 30, null, null, fake, fake, fake, 1 << 30, fake,
+                         null) == bb.BDS_EINVAL  # B == X
+    assert lib.bds_solve(ctypes.byref(d), fake, 16, null, null, fake, ctypes.c_void_p(0x2000), fake, 1 << 30,
+                         fake, null) == bb.BDS_EWORKSPACE
+    mixed = desc(8, 4, 1, prec=1)
+    assert lib.bds_solve(ctypes.byref(mixed), fake, 1 << 30, null, null, fake, ctypes.c_void_p(0x2000), fake,
+                         1 << 30, fake, null) == bb.BDS_EINVAL  # refinement needs A
+    assert lib.bds_backward(ctypes.byref(d), fake, 1 << 30, null, null, fake, fake, null, fake, fake, fake,
+                            1 << 30, fake, null) == bb.BDS_EINVAL
+    bad = desc(0, 4, 1)
+    assert lib.bds_factor(ctypes.byref(bad), fake, fake, fake, 1 << 20, fake, null) == bb.BDS_EINVAL
