@@ -1,0 +1,312 @@
+"""Benchmark: factor + solve throughput of the MI355X block-tridiagonal SPD solver.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+One step is one bds_factor (recursive factorisation, the paper's Alg. 4) plus
+one bds_solve (recursive solve, Alg. 5-7) of all d right-hand sides, with the
+inputs resident in device memory.  Workspaces are allocated once before the
+timed region (the paper's "Init" phase, which it also leaves out of its
+totals).  Prints one JSON line.
+
+Workloads (seeded synthetic inputs, see paper_2509_03015_amd/inputs.py):
+  fp64     plain FP64, N=16384, n=128, d=16, block diagonally dominant
+           (A_ii = G G^T/n + 5I, A_{i+1,i} ~ N(0,1)/sqrt(n)); the default.
+  f32-k1e4 FP32 factor + FP64 refinement, N=16384, n=256, d=1, Kalman-smoother
+           Hessian at kappa ~ 1e4 (likewise f32-k1e2, f32-k1e6, f64-k1e4 ...).
+
+The "roofline" object is for the kernel with the largest share of the step,
+timed live with HIP events through the library's bds_trace_* calls; its
+algorithmic flops and bytes come from the per-kernel model below, enumerated
+over the reduction levels.  "cpu_baseline" times the CPU oracle (single
+thread, plain C) on a leading sub-chain of the same system and scales it to
+the whole workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "factor+solve solves/s and TFLOP/s vs plain FP64 at rel. error ≤1e-10, 1 GPU"
+
+# MI355X published peaks.
+PEAK = {"hbm": 8000.0,                                   # GB/s
+        "mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16": 2500.0}  # TFLOP/s
+
+WORKLOADS = {
+    "fp64": dict(kind="dd", N=16384, n=128, d=16, prec="f64"),
+    "f32-k1e2": dict(kind="kalman", N=16384, n=256, d=1, prec="f32", kappa=1e2),
+    "f32-k1e4": dict(kind="kalman", N=16384, n=256, d=1, prec="f32", kappa=1e4),
+    "f32-k1e6": dict(kind="kalman", N=16384, n=256, d=1, prec="f32", kappa=1e6),
+    "f64-k1e4": dict(kind="kalman", N=16384, n=256, d=1, prec="f64", kappa=1e4),
+}
+
+
+def levels(N: int, nstar: int):
+    """Block counts M of the reduction levels (odd positions eliminated) and the coarse size."""
+    Ms = []
+    M = N
+    while M > nstar:
+        Ms.append(M)
+        M = (M + 1) // 2
+    return Ms, M
+
+
+def kernel_model(N: int, n: int, d: int, nstar: int, esize: int):
+    """Algorithmic flops and HBM bytes per step of each kernel.
+
+    Per interior block (E = M // 2 per level), with n x n blocks of esize bytes:
+      fac_diag    potrf n^3/3 + triangular inverse n^3/3; reads the lower
+                  triangle of A_ii, writes L^-1 (lower):        n^2 * esize
+      fac_couple  two triangular x dense products, n^3 each; reads L^-1 (half)
+                  and both coupling blocks, writes both solved couplings
+      fac_schur   per separator: two symmetric rank-n updates (n^3 each, lower
+                  half) and one cross product 2 n^3; reads A_jj (half) and
+                  three solved couplings, writes the next level's two blocks
+      sol_fwd_int L^-1 B_i: n^2 d; reads L^-1 (half) and B_i, writes Y_i
+      sol_fwd_sep two products 4 n^2 d; reads 2 couplings, 2 Y, B_j, writes B'_j
+      sol_bwd     two products and L^-T: 5 n^2 d; reads 2 couplings, L^-1
+                  (half), Y_i, two X, writes X_i and copies a separator
+    """
+    Ms, Mc = levels(N, nstar)
+    nn = n * n
+    f, b = {}, {}
+
+    def add(k, fl, by):
+        f[k] = f.get(k, 0.0) + fl
+        b[k] = b.get(k, 0.0) + by
+
+    v = 8 * n * d  # one FP64 right-hand-side block
+    for M in Ms:
+        E, Mn = M // 2, (M + 1) // 2
+        Er = (M - 1) // 2          # interiors with a right coupling
+        add("fac_diag", E * (2.0 / 3.0) * n ** 3, E * nn * esize)
+        add("fac_couple", (E + Er) * float(n) ** 3, E * 0.5 * nn * esize + (E + Er) * 2 * nn * esize)
+        add("fac_schur", Mn * 2.0 * n ** 3 + (Mn - 1) * 2.0 * n ** 3,
+            Mn * 0.5 * nn * 8 + (E + 2 * Er) * nn * esize + (2 * Mn - 1) * nn * esize)
+        add("sol_fwd_int", E * float(nn) * d, E * (0.5 * nn * esize + 2 * v))
+        add("sol_fwd_sep", (E + Er) * 2.0 * nn * d, (E + Er) * (nn * esize + v) + Mn * 2 * v)
+        add("sol_bwd", E * float(nn) * d + (E + Er) * 2.0 * nn * d,
+            E * (0.5 * nn * esize + 4 * v) + (E + Er) * (nn * esize + v))
+    # coarse system, sequential block Cholesky in FP64
+    add("coarse_factor", Mc * (7.0 / 3.0) * n ** 3, Mc * 3 * nn * 8)
+    add("coarse_solve", Mc * 6.0 * nn * d, Mc * (2 * nn * 8 + 3 * v))
+    return f, b
+
+
+KERNEL_BOUND = {"fac_diag": "mfma", "fac_couple": "mfma", "fac_schur": "mfma", "coarse_factor": "mfma",
+                "sol_fwd_int": "hbm", "sol_fwd_sep": "hbm", "sol_bwd": "hbm", "coarse_solve": "hbm",
+                "residual": "hbm", "axpy_norm": "hbm"}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_03015_amd", "csrc", "bds_kernels.hip")
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("bds_kernels.hip", "bds_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2509_03015_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it matches the current source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_inputs(w: dict, seed: int = 0):
+    from paper_2509_03015_amd import inputs
+    if w["kind"] == "dd":
+        return inputs.gen_dd(w["N"], w["n"], w["d"], seed=seed)
+    rho = inputs.KALMAN_RHO[w["n"]][w["kappa"]]
+    return inputs.gen_kalman(w["N"], w["n"], w["d"], rho, seed=seed)
+
+
+def cpu_baseline(Ad, As, B, budget_s: float = 15.0):
+    """Oracle factor + solve on the leading sub-chain of Ns blocks, scaled to the full N."""
+    import oracle
+    N = Ad.shape[0]
+    Ns = min(N, 64)
+    while True:
+        t0 = time.perf_counter()
+        oracle.solve(Ad[:Ns], As[:Ns - 1], B[:Ns])
+        dt = time.perf_counter() - t0
+        if Ns >= N or dt * 2 > budget_s / 2:
+            break
+        Ns = min(N, Ns * 2)
+    per_block = dt / Ns
+    full_s = per_block * N
+    return {"value": 1.0 / full_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 block-Cholesky factor + solve of the leading {Ns} of {N} blocks "
+                      f"({dt:.2f} s, one thread), scaled by {N / Ns:g} to the full chain"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fp64", choices=sorted(WORKLOADS))
+    ap.add_argument("--nstar", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a device copy of this size (counter calibration) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2509_03015_amd import _binding as bb
+    from paper_2509_03015_amd import solver
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    bb.load()
+
+    if args.copy_gib > 0:
+        nel = int(args.copy_gib * (1 << 30)) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nel * 8, "copy_bytes_written": nel * 8, "launches": 3}))
+        return
+
+    w = WORKLOADS[args.workload]
+    N, n, d = w["N"], w["n"], w["d"]
+    t_gen = time.perf_counter()
+    Ad, As, Xt, B = make_inputs(w)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] workload {args.workload}: N={N} n={n} d={d} prec={w['prec']} "
+          f"(inputs {t_gen:.1f} s)", file=sys.stderr, flush=True)
+
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Ad_t, As_t, B_t = to(Ad), to(As), to(B)
+    X_t = torch.empty_like(B_t)
+
+    t_init = time.perf_counter()
+    F = solver.factor(Ad_t, As_t, prec=w["prec"], nstar=args.nstar)
+    F.solve(B_t, out=X_t)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
+
+    for _ in range(args.warmup):
+        F.refactor()
+        F.solve(B_t, out=X_t, check=False)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done", file=sys.stderr, flush=True)
+
+    trace = not args.no_trace
+    if trace:
+        bb.trace_enable(args.steps * 4096)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        F.refactor()
+        F.solve(B_t, out=X_t, check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    kern, dropped = bb.trace_read() if trace else ({}, 0)
+    if trace:
+        bb.trace_enable(0)
+    info = F.check("bench")
+    ms_step = ms_total / args.steps
+
+    X = X_t.cpu().numpy()
+    relerr = float(np.linalg.norm(X - Xt) / np.linalg.norm(Xt))
+
+    esize = {"f64": 8, "f32": 4, "bf16": 2}[w["prec"]]
+    nstar_eff = args.nstar if args.nstar > 0 else 1
+    flops, bytes_ = kernel_model(N, n, d, nstar_eff, esize)
+    iters = max(int(info.get("iters", 0)), 0)
+    tot_flops = sum(flops[k] for k in flops if k.startswith("fac") or k == "coarse_factor") + \
+        (1 + iters) * sum(flops[k] for k in flops if k.startswith("sol") or k == "coarse_solve")
+
+    roof = None
+    kernels = {}
+    if kern:
+        for k, (cnt, ms) in kern.items():
+            kernels[k] = {"launches_per_step": cnt / args.steps, "ms_per_step": ms / args.steps}
+        timed = {k: v for k, v in kern.items() if k in KERNEL_BOUND}
+        dom = max(timed, key=lambda k: timed[k][1])
+        cnt, ms = timed[dom]
+        per_step_launches = cnt / args.steps
+        avg_ms = ms / cnt
+        bound = KERNEL_BOUND[dom]
+        solve_mult = (1 + iters) if dom.startswith("sol") or dom == "coarse_solve" else 1
+        if bound == "mfma":
+            alg = flops[dom] * solve_mult / (per_step_launches)
+            achieved = alg / (avg_ms * 1e-3) / 1e12
+            peak = PEAK["mfma_" + ("f64" if esize == 8 else "f32")]
+            unit = "TFLOP/s"
+        else:
+            alg = bytes_[dom] * solve_mult / per_step_launches
+            achieved = alg / (avg_ms * 1e-3) / 1e9
+            peak = PEAK["hbm"]
+            unit = "GB/s"
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                "traffic": measured_traffic(dom, args.workload), "kernel": dom,
+                "avg_launch_ms": avg_ms, "launches_per_step": per_step_launches,
+                "algorithmic_per_launch": alg, "share_of_step": (ms / args.steps) / ms_step}
+
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_step,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w["prec"],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "n": n, "d": d, "prec": w["prec"],
+                   "generator": w["kind"], **({"kappa": w["kappa"]} if "kappa" in w else {}),
+                   "nstar": nstar_eff},
+        "tflops": tot_flops / (ms_step * 1e-3) / 1e12,
+        "relerr_vs_manufactured": relerr,
+        "refine_iters": iters if w["prec"] != "f64" else 0,
+        "wall_s_timed": wall,
+        "init_s": t_init,
+        "roofline": roof,
+        "kernels": kernels,
+        "trace_dropped": dropped,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(Ad, As, B)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

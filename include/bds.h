@@ -175,6 +175,30 @@ int bds_solve_batched(int64_t K, const bds_desc* descs, const void* factor_ws,
                       const double* const* B, double* const* X, void* solve_ws,
                       size_t solve_bytes, bds_info* info, void* stream);
 
+/*
+ * Kernel timing, for diagnostics and benchmarking; it does not change any
+ * result.  bds_trace_enable(max_launches > 0) creates 2 * max_launches HIP
+ * events on the current device and from then on brackets every kernel launch
+ * of the library with two of them, recorded on the launch stream.  Launches
+ * beyond the pool are not timed and are counted as dropped.
+ * bds_trace_enable(0) stops timing and destroys the events.  Returns BDS_OK,
+ * BDS_EINVAL (max_launches < 0 or > 2^20) or BDS_EHIP.
+ */
+int bds_trace_enable(int64_t max_launches);
+
+/*
+ * Waits for every timed launch, then reports per-kernel totals and clears the
+ * record.  For up to max_kernels distinct kernel names k: names + 64 * k
+ * receives the NUL-terminated name (host buffer of 64 * max_kernels chars),
+ * launches[k] the number of timed launches and total_ms[k] their summed
+ * event-to-event time in milliseconds (host arrays).  *n_kernels receives the
+ * number of distinct names (which may exceed max_kernels) and *dropped, if
+ * not NULL, the launches that were not timed.  Returns BDS_OK, BDS_EINVAL or
+ * BDS_EHIP (an event could not be read; the other totals are still written).
+ */
+int bds_trace_read(int64_t max_kernels, char* names, int64_t* launches, double* total_ms, int64_t* n_kernels,
+                   int64_t* dropped);
+
 /* Library version string and the gfx target it was built for. */
 const char* bds_version(void);
 

@@ -7,7 +7,7 @@ the library; the first solver call does, and raises if it is not built.
 
 
 def __getattr__(name):
-    if name in ("factor", "solve", "Factor", "BdsError", "PRECISIONS"):
+    if name in ("factor", "solve", "Factor", "BdsError", "PRECISIONS", "factor_batched", "BatchedFactor"):
         from . import solver
         return getattr(solver, name)
     raise AttributeError(name)

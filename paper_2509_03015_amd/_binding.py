@@ -19,7 +19,7 @@ BDS_F64, BDS_F32, BDS_BF16 = 0, 1, 2
 
 # Every function declared in include/bds.h.
 EXPORTS = ("bds_workspace_size", "bds_factor", "bds_solve", "bds_backward", "bds_batched_workspace_size",
-           "bds_factor_batched", "bds_solve_batched", "bds_version")
+           "bds_factor_batched", "bds_solve_batched", "bds_trace_enable", "bds_trace_read", "bds_version")
 
 
 class BdsDesc(ctypes.Structure):
@@ -51,15 +51,40 @@ def load():
     lib.bds_factor.argtypes = [D, P, P, P, S, P, P]
     lib.bds_solve.argtypes = [D, P, S, P, P, P, P, P, S, P, P]
     lib.bds_backward.argtypes = [D, P, S, P, P, P, P, P, P, P, P, S, P, P]
-    lib.bds_batched_workspace_size.argtypes = [I64, D, PS, PS]
-    lib.bds_factor_batched.argtypes = [I64, D, P, P, P, S, P, P]
-    lib.bds_solve_batched.argtypes = [I64, D, P, S, P, P, P, P, P, S, P, P]
+    lib.bds_factor_batched.argtypes = [I64, P, P, P, P, S, P, P]
+    lib.bds_solve_batched.argtypes = [I64, P, P, S, P, P, P, P, P, S, P, P]
+    lib.bds_batched_workspace_size.argtypes = [I64, P, PS, PS]
+    lib.bds_trace_enable.argtypes = [I64]
+    lib.bds_trace_read.argtypes = [I64, P, P, P, P, P]
     for f in EXPORTS[:-1]:
         getattr(lib, f).restype = ctypes.c_int
     lib.bds_version.argtypes = []
     lib.bds_version.restype = ctypes.c_char_p
     _lib = lib
     return lib
+
+
+def trace_enable(max_launches: int):
+    rc = load().bds_trace_enable(int(max_launches))
+    if rc != BDS_OK:
+        raise RuntimeError(f"bds_trace_enable: {STATUS_NAMES.get(rc, rc)}")
+
+
+def trace_read(max_kernels: int = 64):
+    """Per-kernel (launches, total_ms) of the timed launches since the last read, and the dropped count."""
+    names = ctypes.create_string_buffer(64 * max_kernels)
+    launches = (ctypes.c_int64 * max_kernels)()
+    total = (ctypes.c_double * max_kernels)()
+    nk = ctypes.c_int64(0)
+    dropped = ctypes.c_int64(0)
+    rc = load().bds_trace_read(max_kernels, names, launches, total, ctypes.byref(nk), ctypes.byref(dropped))
+    if rc != BDS_OK:
+        raise RuntimeError(f"bds_trace_read: {STATUS_NAMES.get(rc, rc)}")
+    out = {}
+    for k in range(min(nk.value, max_kernels)):
+        name = names.raw[64 * k: 64 * (k + 1)].split(b"\0", 1)[0].decode()
+        out[name] = (int(launches[k]), float(total[k]))
+    return out, int(dropped.value)
 
 
 def workspace_size(desc: BdsDesc):

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/bds.h"
+#include "bds_host.hpp"
 #include "bds_kernels.hpp"
 #include "bds_plan.hpp"
 
@@ -20,7 +21,7 @@ int check_desc(const bds_desc* d)
     if (d->N < 1 || d->N > (int64_t(1) << 30)) return BDS_EINVAL;
     if (d->n < 1 || d->n > kMaxN) return BDS_EINVAL;
     if (d->d < 1 || d->d > 65536) return BDS_EINVAL;
-    if (d->prec != BDS_F64 && d->prec != BDS_F32) return BDS_EINVAL;
+    if (d->prec != BDS_F64 && d->prec != BDS_F32 && d->prec != BDS_BF16) return BDS_EINVAL;
     if (d->nstar < 0 || d->max_refine < 0 || !(d->refine_tol >= 0) || d->reserved != 0) return BDS_EINVAL;
     return BDS_OK;
 }
@@ -87,35 +88,18 @@ SysPlan make_plan(const bds_desc& d, size_t base_f, size_t base_s)
     return p;
 }
 
-namespace {
-
-#define BDS_TRY(...)                             \
-    do {                                         \
-        hipError_t e_ = (__VA_ARGS__);           \
-        if (e_ != hipSuccess) return BDS_EHIP;   \
-    } while (0)
-
-template <typename T> T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
-template <typename T> const T* at(const void* base, size_t off)
-{
-    return reinterpret_cast<const T*>(static_cast<const char*>(base) + off);
-}
-
-// Level-0 matrices in padded layout: the user's arrays, or their padded copies.
-struct Level0 {
-    const double* Ad;
-    const double* As;
-};
-
 Level0 level0_matrices(const SysPlan& p, const double* Ad, const double* As, const void* fws)
 {
     if (p.packed) return {at<double>(fws, p.Ad0), at<double>(fws, p.As0)};
     return {Ad, As};
 }
 
-template <typename T>
+namespace {
+
+template <typename C>
 int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws, bds_info* info, hipStream_t st)
 {
+    using T = typename Stor<C>::type;
     BDS_TRY(launch_clear_info(info, 1, st));
     if (p.packed) {
         BDS_TRY(launch_pack_blocks(Ad, at<double>(fws, p.Ad0), p.N, (int)p.n, (int)p.np, true, st));
@@ -129,14 +113,14 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
         if (l == 0) {
             FacLv<T, double> r{a0.Ad, a0.As, at<T>(fws, L.Li), at<T>(fws, L.Wl), at<T>(fws, L.Pr),
                                at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, 0, 0, info};
-            BDS_TRY(launch_factor_level<T, double>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                                   units_fac_couple(M, np), units_fac_schur(M, np), np, st));
+            BDS_TRY(launch_factor_level<C, double>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
+                                                   units_fac_couple(M, np, tile_r(np)), units_fac_schur(M, np, tile_r(np)), np, st));
         } else {
             const LevelPlan& P = p.lv[l - 1];
             FacLv<T, T> r{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<T>(fws, L.Li), at<T>(fws, L.Wl),
                           at<T>(fws, L.Pr), at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, (int)l, 0, info};
-            BDS_TRY(launch_factor_level<T, T>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                              units_fac_couple(M, np), units_fac_schur(M, np), np, st));
+            BDS_TRY(launch_factor_level<C, T>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
+                                              units_fac_couple(M, np, tile_r(np)), units_fac_schur(M, np, tile_r(np)), np, st));
         }
     }
     const int Lv = (int)p.lv.size();
@@ -166,15 +150,15 @@ int solve_core(const SysPlan& p, const void* fws, void* sws, const double* B0, d
         double* X = l == 0 ? X0 : at<double>(sws, p.lv[l - 1].Xn);
         recs[l] = SolLv<T>{at<T>(fws, L.Li), at<T>(fws, L.Wl), at<T>(fws, L.Pr), B, at<double>(sws, L.Y),
                            at<double>(sws, L.Bn), at<double>(sws, L.Xn), X, (int)L.M, np, d, 0};
-        BDS_TRY(launch_solve_fwd<T>(recs[l], nullptr, nullptr, nullptr, 1, units_sol_fwd_int((int)L.M, np, d),
-                                    units_sol_fwd_sep((int)L.M, np, d), np, st));
+        BDS_TRY(launch_solve_fwd<T>(recs[l], nullptr, nullptr, nullptr, 1, units_sol_fwd_int((int)L.M, np, d, tile_r(np)),
+                                    units_sol_fwd_sep((int)L.M, np, d, tile_r(np)), np, st));
     }
     CoarseSol c{at<double>(fws, p.Lc), at<double>(fws, p.Lsc),
                 Lv == 0 ? B0 : at<double>(sws, p.lv.back().Bn), at<double>(sws, p.Yc),
                 Lv == 0 ? X0 : at<double>(sws, p.lv.back().Xn), (int)p.Mc, np, d, 0};
     BDS_TRY(launch_coarse_solve(c, nullptr, nullptr, 1, (d + 15) / 16, st));
     for (int l = Lv - 1; l >= 0; --l)
-        BDS_TRY(launch_solve_bwd<T>(recs[l], nullptr, nullptr, 1, units_sol_bwd((int)p.lv[l].M, np, d), np, st));
+        BDS_TRY(launch_solve_bwd<T>(recs[l], nullptr, nullptr, 1, units_sol_bwd((int)p.lv[l].M, d), np, st));
     return BDS_OK;
 }
 
@@ -195,7 +179,7 @@ int refined_solve(const SysPlan& p, const void* fws, const Level0& a0, void* sws
     int iters = 0, converged = 0;
     double prev = HUGE_VAL;
     for (int it = 1; it <= p.max_refine; ++it) {
-        BDS_TRY(launch_residual(ra, nullptr, nullptr, 1, units_resid(N, np, d), np, st));
+        BDS_TRY(launch_residual(ra, nullptr, nullptr, 1, units_resid(N, np, d, tile_r(np)), np, st));
         rc = solve_core<T>(p, fws, sws, R, C, st);
         if (rc != BDS_OK) return rc;
         BDS_TRY(launch_axpy_norm(xa, nullptr, nullptr, 1, N, st));
@@ -203,18 +187,7 @@ int refined_solve(const SysPlan& p, const void* fws, const Level0& a0, void* sws
         BDS_TRY(hipMemcpyAsync(h, nrm + 2 * N, sizeof(h), hipMemcpyDeviceToHost, st));
         BDS_TRY(hipStreamSynchronize(st));
         iters = it;
-        const double cn = std::sqrt(h[0]), xn = std::sqrt(h[1]);
-        if (!(cn == cn) || !(xn == xn)) break;  // NaN: diverged
-        if (cn <= p.refine_tol * xn) {
-            converged = 1;
-            break;
-        }
-        // no longer contracting: the FP64 residual noise floor has been reached
-        if (cn > 0.5 * prev) {
-            converged = cn <= 1e-8 * xn;
-            break;
-        }
-        prev = cn;
+        if (refine_stop(std::sqrt(h[0]), std::sqrt(h[1]), prev, p.refine_tol, converged)) break;
     }
     BDS_TRY(launch_set_refine_info(info, iters, converged, st));
     return BDS_OK;
@@ -304,6 +277,7 @@ int bds_factor(const bds_desc* desc, const double* Ad, const double* As, void* f
     if (factor_bytes < p.factor_bytes) return BDS_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p.prec == BDS_F64) return factor_impl<double>(p, Ad, As, factor_ws, info, st);
+    if (p.prec == BDS_BF16) return factor_impl<bf16x>(p, Ad, As, factor_ws, info, st);
     return factor_impl<float>(p, Ad, As, factor_ws, info, st);
 }
 
@@ -334,28 +308,6 @@ int bds_backward(const bds_desc* desc, const void* factor_ws, size_t factor_byte
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p.prec == BDS_F64) return backward_impl<double>(p, factor_ws, Ad, As, X, dX, dAd, dAs, dB, solve_ws, info, st);
     return backward_impl<float>(p, factor_ws, Ad, As, X, dX, dAd, dAs, dB, solve_ws, info, st);
-}
-
-int bds_batched_workspace_size(int64_t K, const bds_desc* descs, size_t* factor_bytes, size_t* solve_bytes)
-{
-    (void)K; (void)descs; (void)factor_bytes; (void)solve_bytes;
-    return BDS_EINVAL;
-}
-
-int bds_factor_batched(int64_t K, const bds_desc* descs, const double* const* Ad, const double* const* As,
-                       void* factor_ws, size_t factor_bytes, bds_info* info, void* stream)
-{
-    (void)K; (void)descs; (void)Ad; (void)As; (void)factor_ws; (void)factor_bytes; (void)info; (void)stream;
-    return BDS_EINVAL;
-}
-
-int bds_solve_batched(int64_t K, const bds_desc* descs, const void* factor_ws, size_t factor_bytes,
-                      const double* const* Ad, const double* const* As, const double* const* B, double* const* X,
-                      void* solve_ws, size_t solve_bytes, bds_info* info, void* stream)
-{
-    (void)K; (void)descs; (void)factor_ws; (void)factor_bytes; (void)Ad; (void)As; (void)B; (void)X;
-    (void)solve_ws; (void)solve_bytes; (void)info; (void)stream;
-    return BDS_EINVAL;
 }
 
 const char* bds_version(void) { return "libbds 0.1 gfx950"; }

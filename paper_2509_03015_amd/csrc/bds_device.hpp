@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/bds.h"
 
 namespace bds {
@@ -22,10 +24,28 @@ constexpr int kMaxNP = 256;  // largest padded block size
 
 typedef double dx4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
+typedef short sx4 __attribute__((ext_vector_type(4)));
+
+// Compute tags.  double and float compute in their own precision; bf16x
+// stores FP32 but rounds every MFMA operand to bfloat16 (round to nearest
+// even) and accumulates in FP32 (v_mfma_f32_16x16x16_bf16).
+struct bf16x {};
+
+template <typename C> struct Stor { using type = C; };
+template <> struct Stor<bf16x> { using type = float; };
 
 template <typename T> struct AccT;
 template <> struct AccT<double> { using type = dx4; };
 template <> struct AccT<float> { using type = fx4; };
+template <> struct AccT<bf16x> { using type = fx4; };
+
+// FP32 -> bfloat16 bits, round to nearest even; NaN stays NaN.
+__device__ __forceinline__ short bf16_bits(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (short)0x7fc0;
+    return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
 __device__ __forceinline__ dx4 mma(double a, double b, dx4 c)
 {
@@ -61,17 +81,18 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
                                          int64_t lda, const SB* B, int64_t ldb, int m0, int n0,
                                          int k0, int k1, int ncols = 1 << 30)
 {
+    using V = typename Stor<T>::type;
     const int l = lane_id();
     const int i = l & 15, g = l >> 4;
     for (int kc = k0; kc < k1; kc += 16) {
         const int k = kc + 4 * g;
-        T a[RM][4], b[RN][4];
+        V a[RM][4], b[RN][4];
 #pragma unroll
         for (int ta = 0; ta < RM; ++ta) {
             const int m = m0 + 16 * ta + i;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                a[ta][s] = A_MK ? (T)A[(int64_t)m * lda + k + s] : (T)A[(int64_t)(k + s) * lda + m];
+                a[ta][s] = A_MK ? (V)A[(int64_t)m * lda + k + s] : (V)A[(int64_t)(k + s) * lda + m];
         }
 #pragma unroll
         for (int tb = 0; tb < RN; ++tb) {
@@ -79,15 +100,33 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
             const bool ok = !B_MASK || n < ncols;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                b[tb][s] = ok ? (B_NK ? (T)B[(int64_t)n * ldb + k + s] : (T)B[(int64_t)(k + s) * ldb + n])
-                              : (T)0;
+                b[tb][s] = ok ? (B_NK ? (V)B[(int64_t)n * ldb + k + s] : (V)B[(int64_t)(k + s) * ldb + n])
+                              : (V)0;
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
+        if constexpr (std::is_same<T, bf16x>::value) {
+            // one 16x16x16 instruction covers the four k-steps: lane (i, g) supplies k = 4g .. 4g+3
+            sx4 ab[RM], bb[RN];
 #pragma unroll
             for (int ta = 0; ta < RM; ++ta)
 #pragma unroll
-                for (int tb = 0; tb < RN; ++tb) acc[ta][tb] = mma(a[ta][s], b[tb][s], acc[ta][tb]);
+                for (int s = 0; s < 4; ++s) ab[ta][s] = bf16_bits(a[ta][s]);
+#pragma unroll
+            for (int tb = 0; tb < RN; ++tb)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) bb[tb][s] = bf16_bits(b[tb][s]);
+#pragma unroll
+            for (int ta = 0; ta < RM; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < RN; ++tb)
+                    acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab[ta], bb[tb], acc[ta][tb], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int ta = 0; ta < RM; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < RN; ++tb) acc[ta][tb] = mma(a[ta][s], b[tb][s], acc[ta][tb]);
+        }
     }
 }
 
@@ -125,7 +164,8 @@ template <typename T> struct DiagSmem {
     int bad_col;
 };
 
-// Cholesky factor and its inverse for one np x np SPD block, computed by a
+// Cholesky factor and its inverse for one np x np SPD block (compute tag C,
+// storage Stor<C>), computed by a
 // whole 256-thread work-group (4 waves):
 //   D  (np x np, element type In, lower triangle read, ld = np)
 //   Lo (np x np, T): receives the lower Cholesky factor L of D.  It may alias
@@ -137,10 +177,12 @@ template <typename T> struct DiagSmem {
 // inverse (MFMA).  Then L^-1 is built by tile diagonals:
 //   Li[I][J] = -Li[I][I] * sum_{K=J}^{I-1} L[I][K] Li[K][J].
 // Returns the first column whose pivot is not positive, or -1.
-template <typename T, typename In>
-__device__ int diag_factor_wg(const In* D, T* Lo, T* Li, int np, DiagSmem<T>& sm)
+template <typename C, typename In>
+__device__ int diag_factor_wg(const In* D, typename Stor<C>::type* Lo, typename Stor<C>::type* Li, int np,
+                              DiagSmem<typename Stor<C>::type>& sm)
 {
-    using A = typename AccT<T>::type;
+    using T = typename Stor<C>::type;
+    using A = typename AccT<C>::type;
     const int w = wave_id(), l = lane_id();
     const int nt = np / 16;
     if (threadIdx.x == 0) sm.bad_col = -1;
@@ -155,11 +197,11 @@ __device__ int diag_factor_wg(const In* D, T* Lo, T* Li, int np, DiagSmem<T>& sm
         // (a) update tile column J with the finished columns 0..J-1
         for (int I = J + w; I < nt; I += 4) {
             A acc[1][1];
-            acc_zero<T, 1, 1>(acc);
+            acc_zero<C, 1, 1>(acc);
             if (J > 0)
-                wave_mma<T, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np, np, Lo + (int64_t)16 * J * np,
+                wave_mma<C, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np, np, Lo + (int64_t)16 * J * np,
                                               np, 0, 0, 0, 16 * J);
-            acc_foreach<T, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
+            acc_foreach<C, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
                 const T a = (T)D[(int64_t)(16 * I + m) * np + 16 * J + n];
                 if (I == J)
                     sm.d[m][n] = a - v;
@@ -211,10 +253,10 @@ __device__ int diag_factor_wg(const In* D, T* Lo, T* Li, int np, DiagSmem<T>& sm
         // (c) tiles below: L[I][J] = A[I][J] * inv^T
         for (int I = J + 1 + w; I < nt; I += 4) {
             A acc[1][1];
-            acc_zero<T, 1, 1>(acc);
-            wave_mma<T, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np + 16 * J, np, &sm.inv[0][0], 16,
+            acc_zero<C, 1, 1>(acc);
+            wave_mma<C, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np + 16 * J, np, &sm.inv[0][0], 16,
                                           0, 0, 0, 16);
-            acc_foreach<T, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
+            acc_foreach<C, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
                 Lo[(int64_t)(16 * I + m) * np + 16 * J + n] = v;
             });
         }
@@ -225,16 +267,16 @@ __device__ int diag_factor_wg(const In* D, T* Lo, T* Li, int np, DiagSmem<T>& sm
         for (int J = w; J + dlt < nt; J += 4) {
             const int I = J + dlt;
             A acc[1][1];
-            acc_zero<T, 1, 1>(acc);
-            wave_mma<T, 1, 1, true, false>(acc, Lo + (int64_t)16 * I * np, np, Li + 16 * J, np, 0, 0,
+            acc_zero<C, 1, 1>(acc);
+            wave_mma<C, 1, 1, true, false>(acc, Lo + (int64_t)16 * I * np, np, Li + 16 * J, np, 0, 0,
                                            16 * J, 16 * I);
-            acc_foreach<T, 1, 1>(acc, 0, 0, [&](int m, int n, T v) { sm.z[w][m][n] = v; });
+            acc_foreach<C, 1, 1>(acc, 0, 0, [&](int m, int n, T v) { sm.z[w][m][n] = v; });
             wave_sync();
             A acc2[1][1];
-            acc_zero<T, 1, 1>(acc2);
-            wave_mma<T, 1, 1, true, false>(acc2, Li + (int64_t)16 * I * np + 16 * I, np, &sm.z[w][0][0], 16,
+            acc_zero<C, 1, 1>(acc2);
+            wave_mma<C, 1, 1, true, false>(acc2, Li + (int64_t)16 * I * np + 16 * I, np, &sm.z[w][0][0], 16,
                                            0, 0, 0, 16);
-            acc_foreach<T, 1, 1>(acc2, 0, 0, [&](int m, int n, T v) {
+            acc_foreach<C, 1, 1>(acc2, 0, 0, [&](int m, int n, T v) {
                 Li[(int64_t)(16 * I + m) * np + 16 * J + n] = -v;
             });
             wave_sync();

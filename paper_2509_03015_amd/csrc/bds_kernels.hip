@@ -20,6 +20,7 @@
 // are deterministic (no atomics in the arithmetic).
 #include "bds_device.hpp"
 #include "bds_kernels.hpp"
+#include "bds_trace.hpp"
 
 namespace bds {
 
@@ -38,11 +39,15 @@ template <typename S> struct One {
 
 template <typename S> struct Many {
     const S* s;
-    const int64_t* start;  // K + 1 exclusive prefix sums
+    const int64_t* start;  // K + 1 exclusive prefix sums; nullptr: one unit per record
     int K;
     int64_t total;
     __device__ __forceinline__ const S& get(int64_t u, int64_t& local) const
     {
+        if (!start) {
+            local = 0;
+            return s[u];
+        }
         int lo = 0, hi = K - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -56,37 +61,38 @@ template <typename S> struct Many {
     }
 };
 
-static inline int tile_r(int np) { return (np % 32 == 0) ? 2 : 1; }
+int tile_r(int np) { return (np % 32 == 0) ? 2 : 1; }
 
 int64_t units_fac_diag(int M) { return M / 2; }
-int64_t units_fac_couple(int M, int np)
+int64_t units_fac_couple(int M, int np, int R)
 {
-    const int tp = np / (16 * tile_r(np));
+    const int tp = np / (16 * R);
     return (int64_t)(M / 2) * 2 * tp * tp;
 }
-int64_t units_fac_schur(int M, int np)
+int64_t units_fac_schur(int M, int np, int R)
 {
-    const int tp = np / (16 * tile_r(np));
+    const int tp = np / (16 * R);
     return (int64_t)((M + 1) / 2) * (tp * (tp + 1) / 2 + tp * tp);
 }
 static inline int dchunks(int d) { return (d + 15) / 16; }
-int64_t units_sol_fwd_int(int M, int np, int d)
+int64_t units_sol_fwd_int(int M, int np, int d, int R)
 {
-    return (int64_t)(M / 2) * (np / (16 * tile_r(np))) * dchunks(d);
+    return (int64_t)(M / 2) * (np / (16 * R)) * dchunks(d);
 }
-int64_t units_sol_fwd_sep(int M, int np, int d)
+int64_t units_sol_fwd_sep(int M, int np, int d, int R)
 {
-    return (int64_t)((M + 1) / 2) * (np / (16 * tile_r(np))) * dchunks(d);
+    return (int64_t)((M + 1) / 2) * (np / (16 * R)) * dchunks(d);
 }
-int64_t units_sol_bwd(int M, int np, int d) { return (int64_t)(M / 2) * dchunks(d); }
-int64_t units_resid(int N, int np, int d) { return (int64_t)N * (np / (16 * tile_r(np))) * dchunks(d); }
+int64_t units_sol_bwd(int M, int d) { return (int64_t)(M / 2) * dchunks(d); }
+int64_t units_resid(int N, int np, int d, int R) { return (int64_t)N * (np / (16 * R)) * dchunks(d); }
 
 // ---------------------------------------------------------------------------
 // factorisation
 
-template <typename T, typename In, typename Tab>
+template <typename C, typename In, typename Tab>
 __global__ __launch_bounds__(256) void k_fac_diag(Tab tab)
 {
+    using T = typename Stor<C>::type;
     __shared__ DiagSmem<T> sm;
     const int64_t u = blockIdx.x;
     if (u >= tab.total) return;
@@ -95,15 +101,16 @@ __global__ __launch_bounds__(256) void k_fac_diag(Tab tab)
     const int np = s.np;
     const int64_t nn = (int64_t)np * np;
     const int64_t i = 2 * e + 1;
-    const int bad = diag_factor_wg<T, In>(s.Ad + i * nn, s.Wl + e * nn, s.Li + e * nn, np, sm);
+    const int bad = diag_factor_wg<C, In>(s.Ad + i * nn, s.Wl + e * nn, s.Li + e * nn, np, sm);
     if (bad >= 0 && threadIdx.x == 0)
         report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad);
 }
 
-template <typename T, typename In, int R, typename Tab>
+template <typename C, typename In, int R, typename Tab>
 __global__ __launch_bounds__(256) void k_fac_couple(Tab tab)
 {
-    using A = typename AccT<T>::type;
+    using T = typename Stor<C>::type;
+    using A = typename AccT<C>::type;
     const int64_t u = (int64_t)blockIdx.x * 4 + wave_id();
     if (u >= tab.total) return;
     int64_t loc;
@@ -117,27 +124,28 @@ __global__ __launch_bounds__(256) void k_fac_couple(Tab tab)
     const int64_t i = 2 * e + 1;
     const T* Li = s.Li + e * nn;
     A acc[R][R];
-    acc_zero<T, R, R>(acc);
+    acc_zero<C, R, R>(acc);
     if (which == 0) {
         // Wl = Li * A[i,i-1]; Li is lower triangular: k < m0 + 16R
-        wave_mma<T, R, R, true, false>(acc, Li + (int64_t)m0 * np, np, s.As + (i - 1) * nn + n0, np, 0, 0,
+        wave_mma<C, R, R, true, false>(acc, Li + (int64_t)m0 * np, np, s.As + (i - 1) * nn + n0, np, 0, 0,
                                        0, min(np, m0 + 16 * R));
         T* out = s.Wl + e * nn;
-        acc_foreach<T, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
+        acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
     } else {
         if (i + 1 >= s.M) return;
         // Pr = A[i+1,i] * Li^T; Li^T upper: k < n0 + 16R
-        wave_mma<T, R, R, true, true>(acc, s.As + i * nn + (int64_t)m0 * np, np, Li + (int64_t)n0 * np, np,
+        wave_mma<C, R, R, true, true>(acc, s.As + i * nn + (int64_t)m0 * np, np, Li + (int64_t)n0 * np, np,
                                       0, 0, 0, min(np, n0 + 16 * R));
         T* out = s.Pr + e * nn;
-        acc_foreach<T, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
+        acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
     }
 }
 
-template <typename T, typename In, int R, typename Tab>
+template <typename C, typename In, int R, typename Tab>
 __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
 {
-    using A = typename AccT<T>::type;
+    using T = typename Stor<C>::type;
+    using A = typename AccT<C>::type;
     const int64_t u = (int64_t)blockIdx.x * 4 + wave_id();
     if (u >= tab.total) return;
     int64_t loc;
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
     const int rem = (int)(loc % per);
     const int Mn = (s.M + 1) / 2;
     A acc[R][R];
-    acc_zero<T, R, R>(acc);
+    acc_zero<C, R, R>(acc);
     if (rem < tl) {
         int tm = 0;
         while ((tm + 1) * (tm + 2) / 2 <= rem) ++tm;
@@ -158,15 +166,15 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
         const int m0 = 16 * R * tm, n0 = 16 * R * tn;
         if (j >= 1) {
             const T* P = s.Pr + (j - 1) * nn;
-            wave_mma<T, R, R, true, true>(acc, P + (int64_t)m0 * np, np, P + (int64_t)n0 * np, np, 0, 0, 0, np);
+            wave_mma<C, R, R, true, true>(acc, P + (int64_t)m0 * np, np, P + (int64_t)n0 * np, np, 0, 0, 0, np);
         }
         if (2 * j + 1 < s.M) {
             const T* W = s.Wl + j * nn;
-            wave_mma<T, R, R, false, false>(acc, W + m0, np, W + n0, np, 0, 0, 0, np);
+            wave_mma<C, R, R, false, false>(acc, W + m0, np, W + n0, np, 0, 0, 0, np);
         }
         const In* a = s.Ad + 2 * j * nn;
         T* out = s.Adn + j * nn;
-        acc_foreach<T, R, R>(acc, m0, n0, [&](int m, int n, T v) {
+        acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) {
             out[(int64_t)m * np + n] = (T)a[(int64_t)m * np + n] - v;
         });
     } else {
@@ -175,9 +183,9 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
         const int m0 = 16 * R * (t / tp), n0 = 16 * R * (t % tp);
         const T* P = s.Pr + j * nn;
         const T* W = s.Wl + j * nn;
-        wave_mma<T, R, R, true, false>(acc, P + (int64_t)m0 * np, np, W + n0, np, 0, 0, 0, np);
+        wave_mma<C, R, R, true, false>(acc, P + (int64_t)m0 * np, np, W + n0, np, 0, 0, 0, np);
         T* out = s.Asn + j * nn;
-        acc_foreach<T, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
+        acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
     }
 }
 
@@ -590,6 +598,47 @@ __global__ void k_unpack_rhs(const double* src, double* dst, int64_t nblk, int n
     }
 }
 
+// Table-driven packing for batched systems: one work-group per block.
+template <typename Tab>
+__global__ __launch_bounds__(256) void k_pack_tab(Tab tab)
+{
+    const int64_t u = blockIdx.x;
+    if (u >= tab.total) return;
+    int64_t b;
+    const auto& s = tab.get(u, b);
+    const int n = s.n, np = s.np, c = s.cols;
+    if (s.mode == PACK_UNPACK_RHS) {
+        const double* src = s.src + b * (int64_t)np * c;
+        double* dst = s.dst + b * (int64_t)n * c;
+        for (int q = threadIdx.x; q < n * c; q += blockDim.x) dst[q] = src[(q / c) * c + q % c];
+        return;
+    }
+    const int sc = (s.mode == PACK_RHS) ? c : n;     // source columns
+    const int dc = (s.mode == PACK_RHS) ? c : np;    // destination columns
+    const int dr = np;
+    const double* src = s.src + b * (int64_t)n * sc;
+    double* dst = s.dst + b * (int64_t)dr * dc;
+    for (int q = threadIdx.x; q < dr * dc; q += blockDim.x) {
+        const int r = q / dc, cc = q % dc;
+        double v;
+        if (r < n && cc < sc)
+            v = src[(int64_t)r * sc + cc];
+        else
+            v = (s.mode == PACK_DIAG && r == cc) ? 1.0 : 0.0;
+        dst[q] = v;
+    }
+}
+
+// Per-record refinement outcome: ic[2k] = iterations, ic[2k+1] = converged.
+__global__ void k_set_refine_info_tab(bds_info* info, const int* ic, int K)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    info[k].iters = ic[2 * k];
+    info[k].converged = ic[2 * k + 1];
+    if (!ic[2 * k + 1]) atomicCAS(&info[k].status, 0, (int)BDS_ENOCONV);
+}
+
 __global__ void k_clear_info(bds_info* info, int K)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -610,35 +659,36 @@ __global__ void k_set_refine_info(bds_info* info, int iters, int converged)
 
 static inline unsigned grid_waves(int64_t units) { return (unsigned)((units + 3) / 4); }
 
-template <typename T, typename In>
-hipError_t launch_factor_level(const FacLv<T, In>& one, const FacLv<T, In>* tab, const int64_t* sd,
+template <typename C, typename In>
+hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
+                               const FacLv<typename Stor<C>::type, In>* tab, const int64_t* sd,
                                const int64_t* sc, const int64_t* ss, int K, int64_t td, int64_t tc,
                                int64_t ts, int np_max, hipStream_t st)
 {
     const bool r2 = (np_max % 32 == 0);
     if (!tab) {
-        One<FacLv<T, In>> o{one, td};
-        if (td > 0) k_fac_diag<T, In><<<(unsigned)td, 256, 0, st>>>(o);
+        One<FacLv<typename Stor<C>::type, In>> o{one, td};
+        if (td > 0) BDS_TIMED("fac_diag", st, k_fac_diag<C, In><<<(unsigned)td, 256, 0, st>>>(o));
         o.total = tc;
         if (tc > 0) {
-            if (r2) k_fac_couple<T, In, 2><<<grid_waves(tc), 256, 0, st>>>(o);
-            else k_fac_couple<T, In, 1><<<grid_waves(tc), 256, 0, st>>>(o);
+            if (r2) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(o));
+            else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(o));
         }
         o.total = ts;
         if (ts > 0) {
-            if (r2) k_fac_schur<T, In, 2><<<grid_waves(ts), 256, 0, st>>>(o);
-            else k_fac_schur<T, In, 1><<<grid_waves(ts), 256, 0, st>>>(o);
+            if (r2) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(o));
+            else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(o));
         }
     } else {
         // batched: per-record np may differ; 16-row tiles are valid for every np
-        Many<FacLv<T, In>> m{tab, sd, K, td};
-        if (td > 0) k_fac_diag<T, In><<<(unsigned)td, 256, 0, st>>>(m);
+        Many<FacLv<typename Stor<C>::type, In>> m{tab, sd, K, td};
+        if (td > 0) BDS_TIMED("fac_diag", st, k_fac_diag<C, In><<<(unsigned)td, 256, 0, st>>>(m));
         m.start = sc;
         m.total = tc;
-        if (tc > 0) k_fac_couple<T, In, 1><<<grid_waves(tc), 256, 0, st>>>(m);
+        if (tc > 0) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(m));
         m.start = ss;
         m.total = ts;
-        if (ts > 0) k_fac_schur<T, In, 1><<<grid_waves(ts), 256, 0, st>>>(m);
+        if (ts > 0) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(m));
     }
     return hipGetLastError();
 }
@@ -648,13 +698,13 @@ hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* t
 {
     if (!tab) {
         One<CoarseFac<In>> o{one, 1};
-        if (one.np % 32 == 0) k_coarse_factor<In, 2><<<1, 256, 0, st>>>(o);
-        else k_coarse_factor<In, 1><<<1, 256, 0, st>>>(o);
+        if (one.np % 32 == 0) BDS_TIMED("coarse_factor", st, k_coarse_factor<In, 2><<<1, 256, 0, st>>>(o));
+        else BDS_TIMED("coarse_factor", st, k_coarse_factor<In, 1><<<1, 256, 0, st>>>(o));
     } else {
-        // one record per system; identity prefix is not needed (one unit each)
+        // one work-group per record
+        if (K <= 0) return hipSuccess;
         Many<CoarseFac<In>> m{tab, nullptr, K, K};
-        (void)m;
-        return hipErrorNotSupported;
+        BDS_TIMED("coarse_factor", st, k_coarse_factor<In, 1><<<(unsigned)K, 256, 0, st>>>(m));
     }
     return hipGetLastError();
 }
@@ -667,20 +717,20 @@ hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab, const int6
     if (!tab) {
         One<SolLv<T>> o{one, ti};
         if (ti > 0) {
-            if (r2) k_sol_fwd_int<T, 2><<<grid_waves(ti), 256, 0, st>>>(o);
-            else k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(o);
+            if (r2) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2><<<grid_waves(ti), 256, 0, st>>>(o));
+            else BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(o));
         }
         o.total = ts;
         if (ts > 0) {
-            if (r2) k_sol_fwd_sep<T, 2><<<grid_waves(ts), 256, 0, st>>>(o);
-            else k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(o);
+            if (r2) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 2><<<grid_waves(ts), 256, 0, st>>>(o));
+            else BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(o));
         }
     } else {
         Many<SolLv<T>> m{tab, si, K, ti};
-        if (ti > 0) k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(m);
+        if (ti > 0) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(m));
         m.start = ss;
         m.total = ts;
-        if (ts > 0) k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(m);
+        if (ts > 0) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(m));
     }
     return hipGetLastError();
 }
@@ -692,11 +742,11 @@ hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab, const int6
     if (tb <= 0) return hipSuccess;
     if (!tab) {
         One<SolLv<T>> o{one, tb};
-        if (np_max % 32 == 0) k_sol_bwd<T, 2><<<(unsigned)tb, 256, 0, st>>>(o);
-        else k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(o);
+        if (np_max % 32 == 0) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2><<<(unsigned)tb, 256, 0, st>>>(o));
+        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(o));
     } else {
         Many<SolLv<T>> m{tab, sb, K, tb};
-        k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(m);
+        BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(m));
     }
     return hipGetLastError();
 }
@@ -707,11 +757,11 @@ hipError_t launch_coarse_solve(const CoarseSol& one, const CoarseSol* tab, const
     if (tot <= 0) return hipSuccess;
     if (!tab) {
         One<CoarseSol> o{one, tot};
-        if (one.np % 32 == 0) k_coarse_solve<2><<<(unsigned)tot, 256, 0, st>>>(o);
-        else k_coarse_solve<1><<<(unsigned)tot, 256, 0, st>>>(o);
+        if (one.np % 32 == 0) BDS_TIMED("coarse_solve", st, k_coarse_solve<2><<<(unsigned)tot, 256, 0, st>>>(o));
+        else BDS_TIMED("coarse_solve", st, k_coarse_solve<1><<<(unsigned)tot, 256, 0, st>>>(o));
     } else {
         Many<CoarseSol> m{tab, start, K, tot};
-        k_coarse_solve<1><<<(unsigned)tot, 256, 0, st>>>(m);
+        BDS_TIMED("coarse_solve", st, k_coarse_solve<1><<<(unsigned)tot, 256, 0, st>>>(m));
     }
     return hipGetLastError();
 }
@@ -722,11 +772,11 @@ hipError_t launch_residual(const ResidArgs& one, const ResidArgs* tab, const int
     if (tot <= 0) return hipSuccess;
     if (!tab) {
         One<ResidArgs> o{one, tot};
-        if (np_max % 32 == 0) k_residual<2><<<grid_waves(tot), 256, 0, st>>>(o);
-        else k_residual<1><<<grid_waves(tot), 256, 0, st>>>(o);
+        if (np_max % 32 == 0) BDS_TIMED("residual", st, k_residual<2><<<grid_waves(tot), 256, 0, st>>>(o));
+        else BDS_TIMED("residual", st, k_residual<1><<<grid_waves(tot), 256, 0, st>>>(o));
     } else {
         Many<ResidArgs> m{tab, start, K, tot};
-        k_residual<1><<<grid_waves(tot), 256, 0, st>>>(m);
+        BDS_TIMED("residual", st, k_residual<1><<<grid_waves(tot), 256, 0, st>>>(m));
     }
     return hipGetLastError();
 }
@@ -736,14 +786,15 @@ hipError_t launch_axpy_norm(const AxpyArgs& one, const AxpyArgs* tab, const int6
 {
     if (!tab) {
         One<AxpyArgs> o{one, tot};
-        k_axpy_norm<<<(unsigned)tot, 256, 0, st>>>(o);
+        BDS_TIMED("axpy_norm", st, k_axpy_norm<<<(unsigned)tot, 256, 0, st>>>(o));
         o.total = 1;
-        k_norm_final<<<1, 256, 0, st>>>(o);
+        BDS_TIMED("norm_final", st, k_norm_final<<<1, 256, 0, st>>>(o));
     } else {
+        if (tot <= 0) return hipSuccess;
         Many<AxpyArgs> m{tab, start, K, tot};
-        k_axpy_norm<<<(unsigned)tot, 256, 0, st>>>(m);
-        // one unit per record for the final sums: start = 0, 1, 2, ... is implied
-        return hipErrorNotSupported;
+        BDS_TIMED("axpy_norm", st, k_axpy_norm<<<(unsigned)tot, 256, 0, st>>>(m));
+        Many<AxpyArgs> f{tab, nullptr, K, K};
+        BDS_TIMED("norm_final", st, k_norm_final<<<(unsigned)K, 256, 0, st>>>(f));
     }
     return hipGetLastError();
 }
@@ -751,7 +802,7 @@ hipError_t launch_axpy_norm(const AxpyArgs& one, const AxpyArgs* tab, const int6
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(2 * a.N - 1);
-    k_adjoint<<<nb, 256, 0, st>>>(a);
+    BDS_TIMED("adjoint", st, k_adjoint<<<nb, 256, 0, st>>>(a));
     return hipGetLastError();
 }
 
@@ -767,46 +818,61 @@ hipError_t launch_pack_blocks(const double* src, double* dst, int64_t nblk, int 
                               hipStream_t st)
 {
     if (nblk <= 0) return hipSuccess;
-    k_pack_blocks<<<grid_elems(nblk * np * np), 256, 0, st>>>(src, dst, nblk, n, np, diag ? 1 : 0);
+    BDS_TIMED("pack_blocks", st, k_pack_blocks<<<grid_elems(nblk * np * np), 256, 0, st>>>(src, dst, nblk, n, np, diag ? 1 : 0));
     return hipGetLastError();
 }
 
 hipError_t launch_pack_rhs(const double* src, double* dst, int64_t nblk, int n, int np, int d, hipStream_t st)
 {
     if (nblk <= 0) return hipSuccess;
-    k_pack_rhs<<<grid_elems(nblk * np * d), 256, 0, st>>>(src, dst, nblk, n, np, d);
+    BDS_TIMED("pack_rhs", st, k_pack_rhs<<<grid_elems(nblk * np * d), 256, 0, st>>>(src, dst, nblk, n, np, d));
     return hipGetLastError();
 }
 
 hipError_t launch_unpack_rhs(const double* src, double* dst, int64_t nblk, int n, int np, int d, hipStream_t st)
 {
     if (nblk <= 0) return hipSuccess;
-    k_unpack_rhs<<<grid_elems(nblk * n * d), 256, 0, st>>>(src, dst, nblk, n, np, d);
+    BDS_TIMED("unpack_rhs", st, k_unpack_rhs<<<grid_elems(nblk * n * d), 256, 0, st>>>(src, dst, nblk, n, np, d));
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_tab(const PackRec* tab, const int64_t* start, int K, int64_t tot, hipStream_t st)
+{
+    if (tot <= 0) return hipSuccess;
+    Many<PackRec> m{tab, start, K, tot};
+    BDS_TIMED("pack_tab", st, k_pack_tab<<<(unsigned)tot, 256, 0, st>>>(m));
+    return hipGetLastError();
+}
+
+hipError_t launch_set_refine_info_tab(bds_info* info, const int* ic, int K, hipStream_t st)
+{
+    if (K <= 0) return hipSuccess;
+    BDS_TIMED("set_refine_info", st, k_set_refine_info_tab<<<(K + 255) / 256, 256, 0, st>>>(info, ic, K));
     return hipGetLastError();
 }
 
 hipError_t launch_clear_info(bds_info* info, int K, hipStream_t st)
 {
-    k_clear_info<<<(K + 255) / 256, 256, 0, st>>>(info, K);
+    BDS_TIMED("clear_info", st, k_clear_info<<<(K + 255) / 256, 256, 0, st>>>(info, K));
     return hipGetLastError();
 }
 
 hipError_t launch_set_refine_info(bds_info* info, int iters, int converged, hipStream_t st)
 {
-    k_set_refine_info<<<1, 64, 0, st>>>(info, iters, converged);
+    BDS_TIMED("set_refine_info", st, k_set_refine_info<<<1, 64, 0, st>>>(info, iters, converged));
     return hipGetLastError();
 }
 
 // explicit instantiations
-template hipError_t launch_factor_level<double, double>(const FacLv<double, double>&, const FacLv<double, double>*,
-                                                        const int64_t*, const int64_t*, const int64_t*, int,
-                                                        int64_t, int64_t, int64_t, int, hipStream_t);
-template hipError_t launch_factor_level<float, double>(const FacLv<float, double>&, const FacLv<float, double>*,
-                                                       const int64_t*, const int64_t*, const int64_t*, int,
-                                                       int64_t, int64_t, int64_t, int, hipStream_t);
-template hipError_t launch_factor_level<float, float>(const FacLv<float, float>&, const FacLv<float, float>*,
-                                                      const int64_t*, const int64_t*, const int64_t*, int,
-                                                      int64_t, int64_t, int64_t, int, hipStream_t);
+#define BDS_INST_FAC(C, In)                                                                                   \
+    template hipError_t launch_factor_level<C, In>(                                                           \
+        const FacLv<Stor<C>::type, In>&, const FacLv<Stor<C>::type, In>*, const int64_t*, const int64_t*,    \
+        const int64_t*, int, int64_t, int64_t, int64_t, int, hipStream_t);
+BDS_INST_FAC(double, double)
+BDS_INST_FAC(float, double)
+BDS_INST_FAC(float, float)
+BDS_INST_FAC(bf16x, double)
+BDS_INST_FAC(bf16x, float)
 template hipError_t launch_coarse_factor<double>(const CoarseFac<double>&, const CoarseFac<double>*, int,
                                                  hipStream_t);
 template hipError_t launch_coarse_factor<float>(const CoarseFac<float>&, const CoarseFac<float>*, int,

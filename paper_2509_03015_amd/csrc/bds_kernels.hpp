@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "../../include/bds.h"
+#include "bds_device.hpp"
 
 namespace bds {
 
@@ -85,19 +86,33 @@ struct AdjArgs {
     int N, n, np, d;
 };
 
+// Batched packing between the user's n-row blocks and the padded np-row blocks.
+enum { PACK_RHS = 0, PACK_DIAG = 1, PACK_OFFDIAG = 2, PACK_UNPACK_RHS = 3 };
+struct PackRec {
+    const double* src;
+    double* dst;
+    int n, np, cols, mode;  // cols: d for right-hand sides (unused for matrix blocks)
+};
+
 // Work-unit counts per record (waves for wave kernels, work-groups otherwise).
+// R is the wave tile factor: a wave computes (16R) x (16R) output tiles.  The
+// single-system launchers use R = tile_r(np); the table-driven (batched)
+// launchers always use R = 1, which is valid for every np.
+int tile_r(int np);
 int64_t units_fac_diag(int M);
-int64_t units_fac_couple(int M, int np);
-int64_t units_fac_schur(int M, int np);
-int64_t units_sol_fwd_int(int M, int np, int d);
-int64_t units_sol_fwd_sep(int M, int np, int d);
-int64_t units_sol_bwd(int M, int np, int d);
-int64_t units_resid(int N, int np, int d);
+int64_t units_fac_couple(int M, int np, int R);
+int64_t units_fac_schur(int M, int np, int R);
+int64_t units_sol_fwd_int(int M, int np, int d, int R);
+int64_t units_sol_fwd_sep(int M, int np, int d, int R);
+int64_t units_sol_bwd(int M, int d);
+int64_t units_resid(int N, int np, int d, int R);
 
 // Launchers.  tab_dev/start_dev == nullptr: single record passed by value.
 // Otherwise K records at tab_dev with exclusive prefix sums start_dev (K+1).
-template <typename T, typename In>
-hipError_t launch_factor_level(const FacLv<T, In>& one, const FacLv<T, In>* tab_dev,
+// C: compute tag (double, float, or bf16x = FP32 storage with bfloat16 MFMA operands).
+template <typename C, typename In>
+hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
+                               const FacLv<typename Stor<C>::type, In>* tab_dev,
                                const int64_t* start_diag, const int64_t* start_couple,
                                const int64_t* start_schur, int K, int64_t tot_diag,
                                int64_t tot_couple, int64_t tot_schur, int np_max, hipStream_t st);
@@ -132,6 +147,8 @@ hipError_t launch_pack_rhs(const double* src, double* dst, int64_t nblk, int n, 
                            hipStream_t st);
 hipError_t launch_unpack_rhs(const double* src, double* dst, int64_t nblk, int n, int np, int d,
                              hipStream_t st);
+hipError_t launch_pack_tab(const PackRec* tab, const int64_t* start, int K, int64_t tot, hipStream_t st);
+hipError_t launch_set_refine_info_tab(bds_info* info, const int* ic, int K, hipStream_t st);
 hipError_t launch_clear_info(bds_info* info, int K, hipStream_t st);
 hipError_t launch_set_refine_info(bds_info* info, int iters, int converged, hipStream_t st);
 

@@ -33,7 +33,9 @@ constexpr int kDefaultNstar = 1;
 constexpr int kDefaultMaxRefine = 30;
 constexpr double kDefaultRefineTol = 1e-14;
 
-inline size_t matrix_elem_bytes(int prec) { return prec == BDS_F64 ? 8 : (prec == BDS_F32 ? 4 : 2); }
+// Bytes per stored factor element: FP64, or FP32 for both low-precision modes (BF16 rounds
+// MFMA operands, it does not change the storage).
+inline size_t matrix_elem_bytes(int prec) { return prec == BDS_F64 ? 8 : 4; }
 
 struct LevelPlan {
     int64_t M = 0;   // blocks entering the level

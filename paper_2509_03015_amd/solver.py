@@ -78,7 +78,12 @@ class Factor:
         self.fbytes = fbytes
         self.fws = torch.empty(max(fbytes, 1), dtype=torch.uint8, device=self.device)
         self.info_t = torch.zeros(8, dtype=torch.int32, device=self.device)
-        rc = bb.load().bds_factor(ctypes.byref(desc), _ptr(Ad), _ptr(self.As), _ptr(self.fws), fbytes,
+        self.refactor(check=check)
+
+    def refactor(self, check: bool = False):
+        """Run bds_factor again on the same Ad/As into the existing workspace (no allocation)."""
+        desc = self._desc(1)
+        rc = bb.load().bds_factor(ctypes.byref(desc), _ptr(self.Ad), _ptr(self.As), _ptr(self.fws), self.fbytes,
                                   _ptr(self.info_t), _stream_handle(self.device))
         if rc != bb.BDS_OK:
             raise BdsError(rc, "bds_factor")
@@ -148,6 +153,108 @@ class Factor:
         if check and self.prec != "f64":
             self.check("bds_backward")
         return dAd, dAs, dB
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() if t is not None and t.numel() > 0 else 0 for t in ts])
+
+
+class BatchedFactor:
+    """Factor hierarchies of K independent systems of uneven size, built by one launch per kernel and level."""
+
+    def __init__(self, Ads, Ass, prec: str = "f64", nstar: int = 0, check: bool = True):
+        if len(Ads) != len(Ass) or len(Ads) == 0:
+            raise ValueError("need equally many (>= 1) Ad and As tensors")
+        self.K = len(Ads)
+        self.device = Ads[0].device
+        self.prec, self.nstar = prec, int(nstar)
+        self.shapes = []
+        for k, (Ad, As) in enumerate(zip(Ads, Ass)):
+            if Ad.dim() != 3:
+                raise ValueError(f"Ad[{k}] must have shape (N, n, n)")
+            N, n, _ = Ad.shape
+            _check_tensor(Ad, f"Ad[{k}]", (N, n, n), self.device)
+            if N > 1:
+                _check_tensor(As, f"As[{k}]", (N - 1, n, n), self.device)
+            self.shapes.append((int(N), int(n)))
+        self.Ads = list(Ads)
+        self.Ass = [As if N > 1 else None for As, (N, _) in zip(Ass, self.shapes)]
+        self._solve_ws = {}
+        descs = self._descs([1] * self.K)
+        f = ctypes.c_size_t(0)
+        sb = ctypes.c_size_t(0)
+        rc = bb.load().bds_batched_workspace_size(self.K, descs, ctypes.byref(f), ctypes.byref(sb))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_batched_workspace_size")
+        self.fbytes = f.value
+        self.fws = torch.empty(max(self.fbytes, 1), dtype=torch.uint8, device=self.device)
+        self.info_t = torch.zeros((self.K, 8), dtype=torch.int32, device=self.device)
+        self._Ad_p = _ptr_array(self.Ads)
+        self._As_p = _ptr_array(self.Ass)
+        self.refactor(check=check)
+
+    def _descs(self, ds, max_refine: int = 0, refine_tol: float = 0.0):
+        arr = (bb.BdsDesc * self.K)()
+        for k, ((N, n), d) in enumerate(zip(self.shapes, ds)):
+            arr[k] = bb.BdsDesc(N, n, int(d), PRECISIONS[self.prec], self.nstar, int(max_refine), 0,
+                                float(refine_tol))
+        return arr
+
+    def refactor(self, check: bool = False):
+        descs = self._descs([1] * self.K)
+        rc = bb.load().bds_factor_batched(self.K, descs, self._Ad_p, self._As_p, _ptr(self.fws), self.fbytes,
+                                          _ptr(self.info_t), _stream_handle(self.device))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_factor_batched")
+        if check:
+            self.check("bds_factor_batched")
+
+    def info(self) -> list:
+        keys = ("status", "level", "position", "orig_block", "column", "iters", "converged", "reserved")
+        return [dict(zip(keys, row)) for row in self.info_t.cpu().tolist()]
+
+    def check(self, what: str = "bds"):
+        infos = self.info()
+        for k, inf in enumerate(infos):
+            if inf["status"] != bb.BDS_OK:
+                raise BdsError(inf["status"], f"{what} (system {k})", inf)
+        return infos
+
+    def solve(self, Bs, outs=None, max_refine: int = 0, refine_tol: float = 0.0, check: bool = True):
+        if len(Bs) != self.K:
+            raise ValueError(f"expected {self.K} right-hand sides")
+        ds = []
+        for k, (B, (N, n)) in enumerate(zip(Bs, self.shapes)):
+            if B.dim() != 3:
+                raise ValueError(f"B[{k}] must have shape (N, n, d)")
+            _check_tensor(B, f"B[{k}]", (N, n, int(B.shape[2])), self.device)
+            ds.append(int(B.shape[2]))
+        Xs = [torch.empty_like(B) for B in Bs] if outs is None else list(outs)
+        for k, X in enumerate(Xs):
+            _check_tensor(X, f"out[{k}]", tuple(Bs[k].shape), self.device)
+        descs = self._descs(ds, max_refine, refine_tol)
+        key = tuple(ds)
+        ws = self._solve_ws.get(key)
+        if ws is None:
+            f = ctypes.c_size_t(0)
+            sb = ctypes.c_size_t(0)
+            rc = bb.load().bds_batched_workspace_size(self.K, descs, ctypes.byref(f), ctypes.byref(sb))
+            if rc != bb.BDS_OK:
+                raise BdsError(rc, "bds_batched_workspace_size")
+            ws = torch.empty(max(sb.value, 1), dtype=torch.uint8, device=self.device)
+            self._solve_ws[key] = ws
+        rc = bb.load().bds_solve_batched(self.K, descs, _ptr(self.fws), self.fbytes, self._Ad_p, self._As_p,
+                                         _ptr_array(Bs), _ptr_array(Xs), _ptr(ws), ws.numel(), _ptr(self.info_t),
+                                         _stream_handle(self.device))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_solve_batched")
+        if check and self.prec != "f64":
+            self.check("bds_solve_batched")
+        return Xs
+
+
+def factor_batched(Ads, Ass, prec: str = "f64", nstar: int = 0, check: bool = True) -> BatchedFactor:
+    return BatchedFactor(Ads, Ass, prec=prec, nstar=nstar, check=check)
 
 
 def factor(Ad: torch.Tensor, As: torch.Tensor | None, prec: str = "f64", nstar: int = 0,

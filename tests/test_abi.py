@@ -94,3 +94,48 @@ def test_calls_reject_bad_arguments_without_launching(lib):
                             1 << 30, fake, null) == bb.BDS_EINVAL
     bad = desc(0, 4, 1)
     assert lib.bds_factor(ctypes.byref(bad), fake, fake, fake, 1 << 20, fake, null) == bb.BDS_EINVAL
+
+
+def descs_array(specs, prec=0, nstar=0):
+    arr = (bb.BdsDesc * len(specs))()
+    for k, (N, n, d) in enumerate(specs):
+        arr[k] = bb.BdsDesc(N, n, d, prec, nstar, 0, 0, 0.0)
+    return arr
+
+
+def test_batched_workspace_is_sum_of_systems_plus_tables(lib):
+    specs = [(10, 8, 1), (100, 32, 4), (1, 3, 2)]
+    arr = descs_array(specs)
+    f = ctypes.c_size_t(0)
+    s = ctypes.c_size_t(0)
+    assert lib.bds_batched_workspace_size(3, arr, ctypes.byref(f), ctypes.byref(s)) == 0
+    single = [bb.workspace_size(desc(N, n, d)) for N, n, d in specs]
+    assert f.value > sum(x[1] for x in single)
+    assert s.value > sum(x[2] for x in single)
+
+
+def test_batched_rejects_mixed_precision_and_bad_members(lib):
+    f = ctypes.c_size_t(0)
+    s = ctypes.c_size_t(0)
+    arr = descs_array([(10, 8, 1), (20, 16, 1)])
+    arr[1].prec = 1
+    assert lib.bds_batched_workspace_size(2, arr, ctypes.byref(f), ctypes.byref(s)) == bb.BDS_EINVAL
+    arr = descs_array([(10, 8, 1), (0, 16, 1)])
+    assert lib.bds_batched_workspace_size(2, arr, ctypes.byref(f), ctypes.byref(s)) == bb.BDS_EINVAL
+    assert lib.bds_batched_workspace_size(0, arr, ctypes.byref(f), ctypes.byref(s)) == bb.BDS_EINVAL
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    good = descs_array([(10, 8, 1), (20, 16, 1)])
+    ptrs = (ctypes.c_void_p * 2)(0x1000, 0)  # second Ad missing
+    assert lib.bds_factor_batched(2, good, ptrs, ptrs, fake, 1 << 30, fake, null) == bb.BDS_EINVAL
+    ok = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    assert lib.bds_factor_batched(2, good, ok, ok, fake, 16, fake, null) == bb.BDS_EWORKSPACE
+    same = (ctypes.c_void_p * 2)(0x3000, 0x4000)
+    assert lib.bds_solve_batched(2, good, fake, 1 << 30, null, null, same, same, fake, 1 << 30, fake,
+                                 null) == bb.BDS_EINVAL  # B[k] == X[k]
+
+
+def test_trace_enable_bounds(lib):
+    assert lib.bds_trace_enable(-1) == bb.BDS_EINVAL
+    assert lib.bds_trace_enable(1 << 21) == bb.BDS_EINVAL
+    assert lib.bds_trace_enable(0) == bb.BDS_OK

@@ -1,0 +1,129 @@
+"""GPU parity of the mixed-precision form: FP32 reduction levels, FP64 coarse system, FP64 refinement.
+
+Bar: relative error <= 1e-10 against the long-double oracle, for the Kalman-smoother Hessian at
+kappa in {1e2, 1e4, 1e6} (the oracle in long double keeps its own error near 1e-19 * kappa).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2509_03015_amd import inputs
+from tests.dense import relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2509_03015_amd import solver
+    solver.bb.load()
+    return solver
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+def test_f32_refined_kalman_matches_long_double_oracle(S, kappa):
+    _say("mixed kalman n=256 kappa", kappa)
+    N, n, d = 96, 256, 1
+    rho = inputs.KALMAN_RHO[n][kappa]
+    Ad, As, Xt, B = inputs.gen_kalman(N, n, d, rho, seed=2)
+    F = S.factor(dev(Ad), dev(As), prec="f32")
+    X = F.solve(dev(B)).cpu().numpy()
+    inf = F.info()
+    assert inf["status"] == 0 and inf["converged"] == 1, inf
+    assert relerr(X, oracle.solve_ld(Ad, As, B)) <= 1e-10
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4])
+def test_f32_refined_kalman_n32(S, kappa):
+    _say("mixed kalman n=32 kappa", kappa)
+    N, n, d = 700, 32, 4
+    rho = inputs.KALMAN_RHO[n][kappa]
+    Ad, As, _, B = inputs.gen_kalman(N, n, d, rho, seed=3)
+    F = S.factor(dev(Ad), dev(As), prec="f32")
+    X = F.solve(dev(B)).cpu().numpy()
+    assert F.info()["converged"] == 1
+    assert relerr(X, oracle.solve_ld(Ad, As, B)) <= 1e-10
+
+
+@pytest.mark.parametrize("N,n,d", [(1, 16, 1), (2, 17, 2), (37, 8, 3), (64, 40, 17), (129, 64, 1)])
+def test_f32_refined_dd_sweep(S, N, n, d):
+    _say("mixed dd", N, n, d)
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=N + n)
+    F = S.factor(dev(Ad), dev(As) if N > 1 else None, prec="f32")
+    X = F.solve(dev(B)).cpu().numpy()
+    inf = F.info()
+    assert inf["converged"] == 1 and inf["iters"] <= 6, inf
+    assert relerr(X, oracle.solve(Ad, As, B)) <= 1e-12
+
+
+def test_f32_without_refinement_budget_reports_noconv(S):
+    """A refinement cap of one iteration at kappa = 1e6 cannot reach the 1e-14 stopping tolerance."""
+    _say("mixed noconv")
+    rho = inputs.KALMAN_RHO[256][1e6]
+    Ad, As, _, B = inputs.gen_kalman(40, 256, 1, rho, seed=4)
+    F = S.factor(dev(Ad), dev(As), prec="f32")
+    F.solve(dev(B), max_refine=1, check=False)
+    inf = F.info()
+    assert inf["status"] == S.bb.BDS_ENOCONV and inf["converged"] == 0 and inf["iters"] == 1
+
+
+def test_f64_plain_kalman_kappa_1e6_against_long_double(S):
+    """Plain FP64 at kappa = 1e6: the error against the long-double oracle is at the kappa*u floor."""
+    _say("f64 kalman 1e6")
+    rho = inputs.KALMAN_RHO[256][1e6]
+    Ad, As, _, B = inputs.gen_kalman(64, 256, 1, rho, seed=5)
+    F = S.factor(dev(Ad), dev(As))
+    X = F.solve(dev(B)).cpu().numpy()
+    assert relerr(X, oracle.solve_ld(Ad, As, B)) <= 1e6 * 2e-16 * 20
+
+
+@pytest.mark.slow
+def test_f32_full_size_kalman_kappa_1e4_properties(S):
+    """N=16384, n=256, d=1 (the mixed-precision configuration): refinement converges and the backward
+    error is at FP64 level; the manufactured solution is recovered to the kappa*u floor."""
+    _say("mixed full size")
+    rho = inputs.KALMAN_RHO[256][1e4]
+    Ad, As, Xt, B = inputs.gen_kalman(16384, 256, 1, rho, seed=0)
+    F = S.factor(dev(Ad), dev(As), prec="f32")
+    X = F.solve(dev(B)).cpu().numpy()
+    inf = F.info()
+    assert inf["status"] == 0 and inf["converged"] == 1, inf
+    R = B - inputs.block_matvec(Ad, As, X)
+    eta = np.linalg.norm(R) / (np.linalg.norm(Ad) * np.linalg.norm(X) + np.linalg.norm(B))
+    assert eta <= 1e-15
+    assert relerr(X, Xt) <= 1e-10
+
+
+@pytest.mark.parametrize("N,n,d", [(1, 16, 1), (37, 8, 3), (64, 40, 17), (129, 64, 1), (300, 128, 2)])
+def test_bf16_refined_dd_sweep(S, N, n, d):
+    """BF16 MFMA operands with FP32 accumulation; FP64 refinement recovers FP64 accuracy at kappa ~ 4."""
+    _say("bf16 dd", N, n, d)
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=3 * N + n)
+    F = S.factor(dev(Ad), dev(As) if N > 1 else None, prec="bf16")
+    X = F.solve(dev(B)).cpu().numpy()
+    inf = F.info()
+    assert inf["converged"] == 1, inf
+    assert relerr(X, oracle.solve(Ad, As, B)) <= 1e-12
+
+
+def test_bf16_refined_kalman_kappa_1e2(S):
+    _say("bf16 kalman 1e2")
+    rho = inputs.KALMAN_RHO[256][1e2]
+    Ad, As, _, B = inputs.gen_kalman(64, 256, 1, rho, seed=6)
+    F = S.factor(dev(Ad), dev(As), prec="bf16")
+    X = F.solve(dev(B), check=False).cpu().numpy()
+    inf = F.info()
+    print("[bf16 kalman 1e2]", inf, file=sys.stderr, flush=True)
+    assert inf["converged"] == 1, inf
+    assert relerr(X, oracle.solve_ld(Ad, As, B)) <= 1e-10
