@@ -117,8 +117,8 @@ public:
     hipError_t upload(hipStream_t st)
     {
         if (used_ == 0) return hipSuccess;
-        // pageable source: the copy is staged before this call returns
-        return hipMemcpyAsync(dev_, h_.get(), used_, hipMemcpyHostToDevice, st);
+        // ordered on the stream and complete on return, so the host image may be freed after it
+        return hipMemcpyWithStream(dev_, h_.get(), used_, hipMemcpyHostToDevice, st);
     }
     bool overflow() const { return used_ > cap_; }
 

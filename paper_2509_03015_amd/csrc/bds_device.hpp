@@ -4,11 +4,16 @@
 // MFMA conventions (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32, wave64):
 // for lane l let i = l % 16 and g = l / 16.  One instruction multiplies a
 // 16 x 4 A fragment (lane l holds A[i][g]) by a 4 x 16 B fragment (lane l
-// holds B[g][j=i]) into a 16 x 16 accumulator where lane l holds rows
-// 4g .. 4g+3 of column i.  The engine walks K in chunks of 16 and feeds k-step
+// holds B[g][j=i]) into a 16 x 16 accumulator where lane l holds four rows
+// of column i (which four: see acc_row below).  The engine walks K in chunks of 16 and feeds k-step
 // s of a chunk with k = 4g + s, so that each lane reads four consecutive k
 // (a vector load when the operand is contiguous along k); A and B use the same
 // order, so every product term is summed exactly once.
+//
+// Accumulator layouts differ between the instructions: the FP32 and BF16 forms
+// give lane l rows 4g .. 4g+3 of column i (register r -> row 4g + r), whereas
+// the FP64 form interleaves them (register r -> row g + 4r).  acc_row() holds
+// this mapping; every read of an accumulator goes through acc_foreach.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -130,6 +135,12 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
     }
 }
 
+// Row within a 16 x 16 accumulator tile of register r in lane group g.
+template <typename T> __device__ __forceinline__ int acc_row(int g, int r)
+{
+    return std::is_same<T, double>::value ? g + 4 * r : 4 * g + r;
+}
+
 // Visit every element of a wave's accumulator tile: f(row, col, value).
 template <typename T, int RM, int RN, typename F>
 __device__ __forceinline__ void acc_foreach(const typename AccT<T>::type (&acc)[RM][RN], int m0,
@@ -142,7 +153,7 @@ __device__ __forceinline__ void acc_foreach(const typename AccT<T>::type (&acc)[
 #pragma unroll
         for (int tb = 0; tb < RN; ++tb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) f(m0 + 16 * ta + 4 * g + r, n0 + 16 * tb + i, acc[ta][tb][r]);
+            for (int r = 0; r < 4; ++r) f(m0 + 16 * ta + acc_row<T>(g, r), n0 + 16 * tb + i, acc[ta][tb][r]);
 }
 
 __device__ __forceinline__ void report_notspd(bds_info* info, int level, int pos, int orig, int col)
