@@ -70,8 +70,10 @@ def kernel_model(N: int, n: int, d: int, nstar: int, esize: int):
       fac_couple  two triangular x dense products, n^3 each; reads L^-1 (half)
                   and both coupling blocks, writes both solved couplings
       fac_schur   per separator: two symmetric rank-n updates (n^3 each, lower
-                  half) and one cross product 2 n^3; reads A_jj (half) and
-                  three solved couplings, writes the next level's two blocks
+                  half); reads A_jj (half) and two solved couplings, writes
+                  the next level's diagonal block (half)
+      fac_schur_off  per inner separator pair: one product 2 n^3; reads two
+                  solved couplings, writes the next level's coupling block
       sol_fwd_int L^-1 B_i: n^2 d; reads L^-1 (half) and B_i, writes Y_i
       sol_fwd_sep two products 4 n^2 d; reads 2 couplings, 2 Y, B_j, writes B'_j
       sol_bwd     two products and L^-T: 5 n^2 d; reads 2 couplings, L^-1
@@ -91,8 +93,13 @@ def kernel_model(N: int, n: int, d: int, nstar: int, esize: int):
         Er = (M - 1) // 2          # interiors with a right coupling
         add("fac_diag", E * (2.0 / 3.0) * n ** 3, E * nn * esize)
         add("fac_couple", (E + Er) * float(n) ** 3, E * 0.5 * nn * esize + (E + Er) * 2 * nn * esize)
-        add("fac_schur", Mn * 2.0 * n ** 3 + (Mn - 1) * 2.0 * n ** 3,
-            Mn * 0.5 * nn * 8 + (E + 2 * Er) * nn * esize + (2 * Mn - 1) * nn * esize)
+        # diagonal Schur blocks: two lower-half symmetric rank-n updates per separator
+        # (one per neighbouring interior, E + Er in all); read A_jj (half) and the two
+        # solved couplings, write S_jj (half)
+        add("fac_schur", (E + Er) * float(n) ** 3,
+            Mn * 0.5 * nn * 8 + (E + Er) * nn * esize + Mn * 0.5 * nn * esize)
+        # off-diagonal Schur blocks: one product 2 n^3 per inner separator pair
+        add("fac_schur_off", (Mn - 1) * 2.0 * n ** 3, (Mn - 1) * 3 * nn * esize)
         add("sol_fwd_int", E * float(nn) * d, E * (0.5 * nn * esize + 2 * v))
         add("sol_fwd_sep", (E + Er) * 2.0 * nn * d, (E + Er) * (nn * esize + v) + Mn * 2 * v)
         add("sol_bwd", E * float(nn) * d + (E + Er) * 2.0 * nn * d,
@@ -103,7 +110,8 @@ def kernel_model(N: int, n: int, d: int, nstar: int, esize: int):
     return f, b
 
 
-KERNEL_BOUND = {"fac_diag": "mfma", "fac_couple": "mfma", "fac_schur": "mfma", "coarse_factor": "mfma",
+KERNEL_BOUND = {"fac_diag": "mfma", "fac_couple": "mfma", "fac_schur": "mfma", "fac_schur_off": "mfma",
+                "coarse_factor": "mfma",
                 "sol_fwd_int": "hbm", "sol_fwd_sep": "hbm", "sol_bwd": "hbm", "coarse_solve": "hbm",
                 "residual": "hbm", "axpy_norm": "hbm"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_03015_amd", "csrc", "bds_kernels.hip")

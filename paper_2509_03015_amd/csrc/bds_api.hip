@@ -127,12 +127,12 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
     if (Lv == 0) {
         CoarseFac<double> c{a0.Ad, a0.As, at<double>(fws, p.Lc), at<double>(fws, p.Lsc), at<double>(fws, p.Cw),
                             (int)p.Mc, np, 0, 0, info};
-        BDS_TRY(launch_coarse_factor<double>(c, nullptr, 1, st));
+        BDS_TRY(launch_coarse_factor<double>(c, nullptr, 1, np, st));
     } else {
         const LevelPlan& P = p.lv.back();
         CoarseFac<T> c{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<double>(fws, p.Lc), at<double>(fws, p.Lsc),
                        at<double>(fws, p.Cw), (int)p.Mc, np, Lv, 0, info};
-        BDS_TRY(launch_coarse_factor<T>(c, nullptr, 1, st));
+        BDS_TRY(launch_coarse_factor<T>(c, nullptr, 1, np, st));
     }
     return BDS_OK;
 }

@@ -177,6 +177,7 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
         const int64_t *sd, *sc, *ss;
         int64_t td, tc, ts;
         int cnt;
+        int np_max;
     };
     std::vector<LevelTab> lt((size_t)bp.nlev);
     for (int l = 0; l < bp.nlev; ++l) {
@@ -185,6 +186,8 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
             if ((int)bp.sys[k].lv.size() > l) members.push_back(k);
         LevelTab& L = lt[l];
         L.cnt = (int)members.size();
+        L.np_max = 16;
+        for (int k : members) L.np_max = std::max<int>(L.np_max, (int)bp.sys[k].np);
         const size_t m = members.size();
         // level 0 reads the FP64 inputs (or their padded copies), deeper levels the
         // previous level's Schur complement in the factor precision T
@@ -256,14 +259,17 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
         const LevelTab& L = lt[l];
         if (l == 0) {
             BDS_TRY(launch_factor_level<C, double>(FacLv<T, double>{}, static_cast<const FacLv<T, double>*>(L.recs),
-                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, 16, st));
+                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np_max, st));
         } else {
             BDS_TRY(launch_factor_level<C, T>(FacLv<T, T>{}, static_cast<const FacLv<T, T>*>(L.recs), L.sd, L.sc,
-                                              L.ss, L.cnt, L.td, L.tc, L.ts, 16, st));
+                                              L.ss, L.cnt, L.td, L.tc, L.ts, L.np_max, st));
         }
     }
-    BDS_TRY(launch_coarse_factor<double>(CoarseFac<double>{}, c0_dev, (int)c0.size(), st));
-    BDS_TRY(launch_coarse_factor<T>(CoarseFac<T>{}, c1_dev, (int)c1.size(), st));
+    int np0 = 16, np1 = 16;
+    for (const auto& c : c0) np0 = std::max(np0, c.np);
+    for (const auto& c : c1) np1 = std::max(np1, c.np);
+    BDS_TRY(launch_coarse_factor<double>(CoarseFac<double>{}, c0_dev, (int)c0.size(), np0, st));
+    BDS_TRY(launch_coarse_factor<T>(CoarseFac<T>{}, c1_dev, (int)c1.size(), np1, st));
     return BDS_OK;
 }
 

@@ -1,5 +1,4 @@
-// Device-side building blocks for gfx950: the MFMA wave-tile engine and the
-// per-block Cholesky + triangular-inverse routine.
+// Device-side building blocks for gfx950: the MFMA wave-tile engine.
 //
 // MFMA conventions (v_mfma_f64_16x16x4_f64 / v_mfma_f32_16x16x4_f32, wave64):
 // for lane l let i = l % 16 and g = l / 16.  One instruction multiplies a
@@ -165,136 +164,6 @@ __device__ __forceinline__ void report_notspd(bds_info* info, int level, int pos
         info->orig_block = orig;
         info->column = col;
     }
-}
-
-// Shared memory of one work-group running diag_factor_wg.
-template <typename T> struct DiagSmem {
-    T d[16][17];       // diagonal tile being factorised
-    T inv[16][16];     // inverse of its Cholesky factor
-    T z[4][16][16];    // per-wave staging tile
-    int bad_col;
-};
-
-// Cholesky factor and its inverse for one np x np SPD block (compute tag C,
-// storage Stor<C>), computed by a
-// whole 256-thread work-group (4 waves):
-//   D  (np x np, element type In, lower triangle read, ld = np)
-//   Lo (np x np, T): receives the lower Cholesky factor L of D.  It may alias
-//      D only when In == T (each tile is read before it is overwritten).
-//   Li (np x np, T): receives L^-1 (lower, explicit zeros above).
-// Left-looking blocked Cholesky on 16 x 16 tiles: the tile column J is updated
-// with the finished columns (MFMA), its diagonal tile is factorised and
-// inverted on one wave, and the tiles below are multiplied by the transposed
-// inverse (MFMA).  Then L^-1 is built by tile diagonals:
-//   Li[I][J] = -Li[I][I] * sum_{K=J}^{I-1} L[I][K] Li[K][J].
-// Returns the first column whose pivot is not positive, or -1.
-template <typename C, typename In>
-__device__ int diag_factor_wg(const In* D, typename Stor<C>::type* Lo, typename Stor<C>::type* Li, int np,
-                              DiagSmem<typename Stor<C>::type>& sm)
-{
-    using T = typename Stor<C>::type;
-    using A = typename AccT<C>::type;
-    const int w = wave_id(), l = lane_id();
-    const int nt = np / 16;
-    if (threadIdx.x == 0) sm.bad_col = -1;
-    // Upper tiles of Li are zero.
-    for (int t = w; t < nt * nt; t += 4) {
-        const int I = t / nt, J = t % nt;
-        if (J > I)
-            for (int e = l; e < 256; e += 64) Li[(int64_t)(16 * I + e / 16) * np + 16 * J + e % 16] = (T)0;
-    }
-    __syncthreads();
-    for (int J = 0; J < nt; ++J) {
-        // (a) update tile column J with the finished columns 0..J-1
-        for (int I = J + w; I < nt; I += 4) {
-            A acc[1][1];
-            acc_zero<C, 1, 1>(acc);
-            if (J > 0)
-                wave_mma<C, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np, np, Lo + (int64_t)16 * J * np,
-                                              np, 0, 0, 0, 16 * J);
-            acc_foreach<C, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
-                const T a = (T)D[(int64_t)(16 * I + m) * np + 16 * J + n];
-                if (I == J)
-                    sm.d[m][n] = a - v;
-                else
-                    Lo[(int64_t)(16 * I + m) * np + 16 * J + n] = a - v;
-            });
-        }
-        __syncthreads();
-        // (b) factor and invert the diagonal tile on wave 0
-        if (w == 0) {
-            for (int k = 0; k < 16; ++k) {
-                const T piv = sm.d[k][k];
-                if (!(piv > (T)0) && l == 0 && sm.bad_col < 0) sm.bad_col = 16 * J + k;
-                const T lkk = sqrt(piv);
-                T lrk = (T)0;
-                if (l > k && l < 16) lrk = sm.d[l][k] / lkk;
-                wave_sync();
-                if (l > k && l < 16) sm.d[l][k] = lrk;
-                if (l == 0) sm.d[k][k] = lkk;
-                wave_sync();
-                // trailing update d[r][c] -= d[r][k] d[c][k], k < c <= r < 16
-                for (int e = l; e < 256; e += 64) {
-                    const int r = e / 16, c = e % 16;
-                    if (c > k && r >= c) sm.d[r][c] -= sm.d[r][k] * sm.d[c][k];
-                }
-                wave_sync();
-            }
-            // inverse by elimination on the identity: row k /= L[k][k]; row r -= L[r][k] row k
-            for (int e = l; e < 256; e += 64) sm.inv[e / 16][e % 16] = (e / 16 == e % 16) ? (T)1 : (T)0;
-            wave_sync();
-            for (int k = 0; k < 16; ++k) {
-                if (l <= k) sm.inv[k][l] = sm.inv[k][l] / sm.d[k][k];
-                wave_sync();
-                // rows r > k, columns c <= k: (15 - k) * (k + 1) <= 64 updates
-                const int cnt = (15 - k) * (k + 1);
-                if (l < cnt) {
-                    const int r = k + 1 + l / (k + 1), c = l % (k + 1);
-                    sm.inv[r][c] -= sm.d[r][k] * sm.inv[k][c];
-                }
-                wave_sync();
-            }
-            for (int e = l; e < 256; e += 64) {
-                const int r = e / 16, c = e % 16;
-                Lo[(int64_t)(16 * J + r) * np + 16 * J + c] = (c <= r) ? sm.d[r][c] : (T)0;
-                Li[(int64_t)(16 * J + r) * np + 16 * J + c] = sm.inv[r][c];
-            }
-        }
-        __syncthreads();
-        // (c) tiles below: L[I][J] = A[I][J] * inv^T
-        for (int I = J + 1 + w; I < nt; I += 4) {
-            A acc[1][1];
-            acc_zero<C, 1, 1>(acc);
-            wave_mma<C, 1, 1, true, true>(acc, Lo + (int64_t)16 * I * np + 16 * J, np, &sm.inv[0][0], 16,
-                                          0, 0, 0, 16);
-            acc_foreach<C, 1, 1>(acc, 0, 0, [&](int m, int n, T v) {
-                Lo[(int64_t)(16 * I + m) * np + 16 * J + n] = v;
-            });
-        }
-        __syncthreads();
-    }
-    // Li below the diagonal, one tile diagonal at a time
-    for (int dlt = 1; dlt < nt; ++dlt) {
-        for (int J = w; J + dlt < nt; J += 4) {
-            const int I = J + dlt;
-            A acc[1][1];
-            acc_zero<C, 1, 1>(acc);
-            wave_mma<C, 1, 1, true, false>(acc, Lo + (int64_t)16 * I * np, np, Li + 16 * J, np, 0, 0,
-                                           16 * J, 16 * I);
-            acc_foreach<C, 1, 1>(acc, 0, 0, [&](int m, int n, T v) { sm.z[w][m][n] = v; });
-            wave_sync();
-            A acc2[1][1];
-            acc_zero<C, 1, 1>(acc2);
-            wave_mma<C, 1, 1, true, false>(acc2, Li + (int64_t)16 * I * np + 16 * I, np, &sm.z[w][0][0], 16,
-                                           0, 0, 0, 16);
-            acc_foreach<C, 1, 1>(acc2, 0, 0, [&](int m, int n, T v) {
-                Li[(int64_t)(16 * I + m) * np + 16 * J + n] = -v;
-            });
-            wave_sync();
-        }
-        __syncthreads();
-    }
-    return sm.bad_col;
 }
 
 }  // namespace bds

@@ -1,0 +1,205 @@
+// Work-group tile products for the per-level contractions (the trsm of the
+// coupling blocks and the Schur updates of Alg. 3), staged through LDS.
+//
+// A work-group of 4 waves (2 x 2) accumulates an MT x MT output tile
+// C += sum over terms of op(A_t) op(B_t); each wave owns an (MT/2) x (MT/2)
+// sub-tile as (MT/32)^2 MFMA accumulator tiles.  The contraction index k runs
+// over the terms one after the other in chunks of 16: a chunk of both
+// operands (MT x 16 each) is loaded from global memory into registers while
+// the previous chunk is multiplied out of LDS, then stored into the other LDS
+// buffer (double buffering, one barrier per chunk).
+//
+// Operands are given as "rows x k" views: element (r, k) of a view is
+// p[r * ld + k] when kc (k contiguous) or p[k * ld + r] otherwise.  A is
+// viewed with its output row as r, B with its output column as r, so that
+// C[m][n] += sum_k A(m, k) B(n, k).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bds_chol.hpp"
+#include "bds_device.hpp"
+
+namespace bds {
+
+template <typename T> struct View {
+    const T* p;
+    int64_t ld;
+    bool kc;
+};
+
+// One term of a tile product: rows m0.. of A, rows n0.. of B, k in [k0, k1).
+template <typename TA, typename TB> struct Term {
+    View<TA> a;
+    View<TB> b;
+    int k0, k1;  // multiples of 16
+};
+
+template <typename T, int MT> struct GemmSmem {
+    static constexpr int LD = TileLd<T>::value;
+    T a[2][MT * LD];
+    T b[2][MT * LD];
+};
+
+// Elements per thread and operand of one chunk (MT x 16 by 256 threads).
+template <int MT> struct ChunkEpt { static constexpr int value = MT / 16; };
+
+// Global -> registers: the thread's share of rows [r0, r0 + MT) x k [k, k + 16).
+template <typename V, int MT, typename T>
+__device__ __forceinline__ void chunk_load(const View<T>& v, int r0, int k, V (&reg)[ChunkEpt<MT>::value])
+{
+    constexpr int E = ChunkEpt<MT>::value;
+    const int t = threadIdx.x;
+    if (v.kc) {
+        // 16 / E threads per row, E consecutive k each
+        const int row = t / (16 / E), kk = (t % (16 / E)) * E;
+        const T* src = v.p + (int64_t)(r0 + row) * v.ld + k + kk;
+#pragma unroll
+        for (int q = 0; q < E; ++q) reg[q] = (V)src[q];
+    } else {
+        // MT / E threads per k, E consecutive rows each
+        const int kk = t / (MT / E), row = (t % (MT / E)) * E;
+        const T* src = v.p + (int64_t)(k + kk) * v.ld + r0 + row;
+#pragma unroll
+        for (int q = 0; q < E; ++q) reg[q] = (V)src[q];
+    }
+}
+
+// Registers -> LDS (rows x 16, row stride LD), matching chunk_load's split.
+template <int MT, typename V>
+__device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[ChunkEpt<MT>::value])
+{
+    constexpr int E = ChunkEpt<MT>::value;
+    constexpr int LD = TileLd<V>::value;
+    const int t = threadIdx.x;
+    if (kc) {
+        const int row = t / (16 / E), kk = (t % (16 / E)) * E;
+#pragma unroll
+        for (int q = 0; q < E; ++q) dst[row * LD + kk + q] = reg[q];
+    } else {
+        const int kk = t / (MT / E), row = (t % (MT / E)) * E;
+#pragma unroll
+        for (int q = 0; q < E; ++q) dst[(row + q) * LD + kk] = reg[q];
+    }
+}
+
+// Accumulate the terms into acc (wave (wm, wn) of the 2 x 2 arrangement owns
+// rows wm * MT/2 .. and columns wn * MT/2 .. of the tile).  wave_kend is the
+// k from which the wave's own products in term 0 are known to vanish (a
+// triangular operand); those chunks are still loaded for the other waves.
+template <typename C, int MT, int NTERM, typename TA, typename TB>
+__device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT / 32][MT / 32],
+                                                const Term<TA, TB> (&terms)[NTERM], int m0, int n0,
+                                                int wave_kend,
+                                                GemmSmem<typename Stor<C>::type, MT>& sm)
+{
+    using V = typename Stor<C>::type;
+    constexpr int R = MT / 32;
+    constexpr int E = ChunkEpt<MT>::value;
+    constexpr int LD = TileLd<V>::value;
+    const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+
+    static_assert(NTERM == 1 || NTERM == 2, "one or two terms");
+    // chunk c -> (term, k): the chunks of term 0, then those of term 1
+    const int nch0 = (terms[0].k1 - terms[0].k0) / 16;
+    const int nch = nch0 + (NTERM == 2 ? (terms[NTERM - 1].k1 - terms[NTERM - 1].k0) / 16 : 0);
+    auto locate = [&](int c, int& t, int& k) {
+        t = (NTERM == 2 && c >= nch0) ? 1 : 0;
+        k = t == 0 ? terms[0].k0 + 16 * c : terms[NTERM - 1].k0 + 16 * (c - nch0);
+    };
+    // the term's views, chosen with selects (indexing the array with a run-time
+    // index would put it in scratch memory)
+    auto view_a = [&](int t) { return (NTERM == 2 && t) ? terms[NTERM - 1].a : terms[0].a; };
+    auto view_b = [&](int t) { return (NTERM == 2 && t) ? terms[NTERM - 1].b : terms[0].b; };
+    V ra[E], rb[E];
+    if (nch == 0) return;
+    {
+        int t, k;
+        locate(0, t, k);
+        const View<TA> va = view_a(t);
+        const View<TB> vb = view_b(t);
+        chunk_load<V, MT>(va, m0, k, ra);
+        chunk_load<V, MT>(vb, n0, k, rb);
+        chunk_store<MT>(va.kc, sm.a[0], ra);
+        chunk_store<MT>(vb.kc, sm.b[0], rb);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        int t1 = 0, k1 = 0;
+        bool kc_a = true, kc_b = true;
+        if (c + 1 < nch) {
+            locate(c + 1, t1, k1);
+            const View<TA> va = view_a(t1);
+            const View<TB> vb = view_b(t1);
+            kc_a = va.kc;
+            kc_b = vb.kc;
+            chunk_load<V, MT>(va, m0, k1, ra);
+            chunk_load<V, MT>(vb, n0, k1, rb);
+        }
+        int tc, kcur;
+        locate(c, tc, kcur);
+        if (!(tc == 0 && kcur >= wave_kend)) {
+            const V* As = sm.a[c & 1] + (wm * (MT / 2) + i) * LD + 4 * g;
+            const V* Bs = sm.b[c & 1] + (wn * (MT / 2) + i) * LD + 4 * g;
+            if constexpr (std::is_same<C, bf16x>::value) {
+                V a[R][4], b[R][4];
+#pragma unroll
+                for (int ta = 0; ta < R; ++ta) ld4(As + 16 * ta * LD, a[ta]);
+#pragma unroll
+                for (int tb = 0; tb < R; ++tb) ld4(Bs + 16 * tb * LD, b[tb]);
+#pragma unroll
+                for (int ta = 0; ta < R; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < R; ++tb) tile_mac<C>(acc[ta][tb], a[ta], b[tb]);
+            } else {
+                // two k-steps at a time keeps the operand registers at 4 R
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    V a[R][2], b[R][2];
+#pragma unroll
+                    for (int ta = 0; ta < R; ++ta)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) a[ta][q] = As[16 * ta * LD + 2 * h + q];
+#pragma unroll
+                    for (int tb = 0; tb < R; ++tb)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) b[tb][q] = Bs[16 * tb * LD + 2 * h + q];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+#pragma unroll
+                        for (int ta = 0; ta < R; ++ta)
+#pragma unroll
+                            for (int tb = 0; tb < R; ++tb) acc[ta][tb] = mma(a[ta][q], b[tb][q], acc[ta][tb]);
+                }
+            }
+        }
+        if (c + 1 < nch) {
+            chunk_store<MT>(kc_a, sm.a[(c + 1) & 1], ra);
+            chunk_store<MT>(kc_b, sm.b[(c + 1) & 1], rb);
+        }
+        __syncthreads();
+    }
+}
+
+// Visit every element of the work-group tile owned by the calling wave.
+template <typename C, int MT, typename F>
+__device__ __forceinline__ void wg_tile_foreach(const typename AccT<C>::type (&acc)[MT / 32][MT / 32], int m0,
+                                                int n0, F f)
+{
+    constexpr int R = MT / 32;
+    const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    acc_foreach<C, R, R>(acc, m0 + wm * (MT / 2), n0 + wn * (MT / 2), f);
+}
+
+// Map the launch's block index to a work index so that consecutive work
+// indices run on the same XCD (blocks are dealt round-robin over the 8 XCDs),
+// which keeps operands shared by neighbouring work items in one L2.
+__device__ __forceinline__ int64_t xcd_local_index(int64_t bid, int64_t nblocks)
+{
+    const int64_t xcd = bid & 7, idx = bid >> 3;
+    const int64_t per = nblocks >> 3, rem = nblocks & 7;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+}  // namespace bds

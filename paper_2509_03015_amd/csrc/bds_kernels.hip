@@ -18,7 +18,9 @@
 //                  from the coarser level (the final Assemble of Alg. 7).
 // Each separator receives its two contributions in a fixed order, so results
 // are deterministic (no atomics in the arithmetic).
+#include "bds_chol.hpp"
 #include "bds_device.hpp"
+#include "bds_gemm.hpp"
 #include "bds_kernels.hpp"
 #include "bds_trace.hpp"
 
@@ -89,11 +91,13 @@ int64_t units_resid(int N, int np, int d, int R) { return (int64_t)N * (np / (16
 // ---------------------------------------------------------------------------
 // factorisation
 
-template <typename C, typename In, typename Tab>
-__global__ __launch_bounds__(256) void k_fac_diag(Tab tab)
+// Two work-groups per CU for blocks up to 128 (three waves per SIMD).
+template <typename C, typename In, int NT, typename Tab>
+__global__ __launch_bounds__(chol_threads<NT>())
+__attribute__((amdgpu_waves_per_eu(NT <= 8 ? 3 : 1))) void k_fac_diag(Tab tab)
 {
     using T = typename Stor<C>::type;
-    __shared__ DiagSmem<T> sm;
+    __shared__ CholSmem<T, NT> sm;
     const int64_t u = blockIdx.x;
     if (u >= tab.total) return;
     int64_t e;
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(256) void k_fac_diag(Tab tab)
     const int np = s.np;
     const int64_t nn = (int64_t)np * np;
     const int64_t i = 2 * e + 1;
-    const int bad = diag_factor_wg<C, In>(s.Ad + i * nn, s.Wl + e * nn, s.Li + e * nn, np, sm);
+    const int bad = chol_inv_block<C, NT, CholWaves<NT>::value, In>(s.Ad + i * nn, s.Li + e * nn, np, sm);
     if (bad >= 0 && threadIdx.x == 0)
         report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad);
 }
@@ -189,13 +193,118 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
     }
 }
 
+// Work-group versions of k_fac_couple / k_fac_schur for block sizes that are
+// a multiple of the macro tile MT (see bds_gemm.hpp).
+//   couple: unit = (interior e, product in {Wl, Pr}, macro tile)
+//   schur, DIAG: unit = (separator j, lower macro tile of S_jj)
+//   schur, !DIAG: unit = (separator j < Mn - 1, macro tile of S_{j+1,j})
+int64_t units_fac_couple_wg(int M, int np, int MT)
+{
+    const int tp = np / MT;
+    return (int64_t)(M / 2) * 2 * tp * tp;
+}
+int64_t units_fac_schur_wg(int M, int np, int MT, bool diag)
+{
+    const int tp = np / MT, Mn = (M + 1) / 2;
+    return diag ? (int64_t)Mn * (tp * (tp + 1) / 2) : (int64_t)(Mn - 1) * tp * tp;
+}
+
+template <typename C, typename In, int MT, typename Tab>
+__global__ __launch_bounds__(256) void k_fac_couple_wg(Tab tab)
+{
+    using T = typename Stor<C>::type;
+    using Acc = typename AccT<C>::type;
+    constexpr int R = MT / 32;
+    __shared__ GemmSmem<T, MT> sm;
+    const int64_t u = xcd_local_index(blockIdx.x, gridDim.x);
+    if (u >= tab.total) return;
+    int64_t loc;
+    const auto& s = tab.get(u, loc);
+    const int np = s.np, tp = np / MT;
+    const int64_t nn = (int64_t)np * np;
+    const int64_t e = loc / (2 * tp * tp);
+    const int rem = (int)(loc % (2 * tp * tp));
+    const int which = rem / (tp * tp), t = rem % (tp * tp);
+    const int m0 = MT * (t / tp), n0 = MT * (t % tp);
+    const int64_t i = 2 * e + 1;
+    if (which == 1 && i + 1 >= s.M) return;
+    const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    const T* Li = s.Li + e * nn;
+    Acc acc[R][R];
+    acc_zero<C, R, R>(acc);
+    T* out;
+    if (which == 0) {
+        // Wl = Li A[i,i-1]: Li is lower triangular, so k < m0 + MT
+        const Term<T, In> terms[1] = {{{Li, np, true}, {s.As + (i - 1) * nn, np, false}, 0, min(np, m0 + MT)}};
+        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, m0 + (wm + 1) * (MT / 2), sm);
+        out = s.Wl + e * nn;
+    } else {
+        // Pr = A[i+1,i] Li^T: k < n0 + MT
+        const Term<In, T> terms[1] = {{{s.As + i * nn, np, true}, {Li, np, true}, 0, min(np, n0 + MT)}};
+        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, n0 + (wn + 1) * (MT / 2), sm);
+        out = s.Pr + e * nn;
+    }
+    wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
+}
+
+template <typename C, typename In, int MT, bool DIAG, typename Tab>
+__global__ __launch_bounds__(256) void k_fac_schur_wg(Tab tab)
+{
+    using T = typename Stor<C>::type;
+    using Acc = typename AccT<C>::type;
+    constexpr int R = MT / 32;
+    __shared__ GemmSmem<T, MT> sm;
+    const int64_t u = xcd_local_index(blockIdx.x, gridDim.x);
+    if (u >= tab.total) return;
+    int64_t loc;
+    const auto& s = tab.get(u, loc);
+    const int np = s.np, tp = np / MT;
+    const int64_t nn = (int64_t)np * np;
+    Acc acc[R][R];
+    acc_zero<C, R, R>(acc);
+    if constexpr (DIAG) {
+        const int per = tp * (tp + 1) / 2;
+        const int64_t j = loc / per;
+        const int rem = (int)(loc % per);
+        int tm = 0;
+        while ((tm + 1) * (tm + 2) / 2 <= rem) ++tm;
+        const int tn = rem - tm * (tm + 1) / 2;
+        const int m0 = MT * tm, n0 = MT * tn;
+        // S_jj = A_jj - Pr(j-1) Pr(j-1)^T - Wl(j)^T Wl(j); absent terms have no chunks
+        const bool left = j >= 1, right = 2 * j + 1 < s.M;
+        const T* P = left ? s.Pr + (j - 1) * nn : s.Pr;
+        const T* W = right ? s.Wl + j * nn : s.Wl;
+        const Term<T, T> terms[2] = {{{P, np, true}, {P, np, true}, 0, left ? np : 0},
+                                     {{W, np, false}, {W, np, false}, 0, right ? np : 0}};
+        wg_tile_product<C, MT, 2>(acc, terms, m0, n0, np, sm);
+        const In* a = s.Ad + 2 * j * nn;
+        T* out = s.Adn + j * nn;
+        wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) {
+            out[(int64_t)m * np + n] = (T)a[(int64_t)m * np + n] - v;
+        });
+    } else {
+        const int64_t j = loc / (tp * tp);
+        const int t = (int)(loc % (tp * tp));
+        const int m0 = MT * (t / tp), n0 = MT * (t % tp);
+        // S_{j+1,j} = -Pr(j) Wl(j)
+        const T* P = s.Pr + j * nn;
+        const T* W = s.Wl + j * nn;
+        const Term<T, T> terms[1] = {{{P, np, true}, {W, np, false}, 0, np}};
+        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, np, sm);
+        T* out = s.Asn + j * nn;
+        wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
+    }
+}
+
 // Coarse system: C_i = A_ii - Lsc[i-1] Lsc[i-1]^T, Lc[i] = chol(C_i)^-1,
 // Lsc[i] = A_{i+1,i} Lc[i]^T.  One work-group per system.
-template <typename In, int R, typename Tab>
-__global__ __launch_bounds__(256) void k_coarse_factor(Tab tab)
+template <typename In, int NT, int R, typename Tab>
+__global__ __launch_bounds__(chol_threads<NT>()) void k_coarse_factor(Tab tab)
 {
     using A = typename AccT<double>::type;
-    __shared__ DiagSmem<double> sm;
+    constexpr int W = CholWaves<NT>::value;
+    constexpr int WB = W + 1;  // waves in the block
+    __shared__ CholSmem<double, NT> sm;
     const int64_t u = blockIdx.x;
     if (u >= tab.total) return;
     int64_t loc;
@@ -204,7 +313,7 @@ __global__ __launch_bounds__(256) void k_coarse_factor(Tab tab)
     const int64_t nn = (int64_t)np * np;
     for (int i = 0; i < s.Mc; ++i) {
         const In* a = s.Ad + i * nn;
-        for (int t = w; t < tp * tp; t += 4) {
+        for (int t = w; t < tp * tp; t += WB) {
             const int m0 = 16 * R * (t / tp), n0 = 16 * R * (t % tp);
             A acc[R][R];
             acc_zero<double, R, R>(acc);
@@ -219,12 +328,12 @@ __global__ __launch_bounds__(256) void k_coarse_factor(Tab tab)
         }
         __syncthreads();
         double* Lci = s.Lc + (int64_t)i * nn;
-        const int bad = diag_factor_wg<double, double>(s.Cw, s.Cw, Lci, np, sm);
+        const int bad = chol_inv_block<double, NT, W, double>(s.Cw, Lci, np, sm);
         if (bad >= 0 && threadIdx.x == 0)
             report_notspd(s.info, s.level, i, i << s.level, bad);
         if (i + 1 < s.Mc) {
             const In* c = s.As + (int64_t)i * nn;
-            for (int t = w; t < tp * tp; t += 4) {
+            for (int t = w; t < tp * tp; t += WB) {
                 const int m0 = 16 * R * (t / tp), n0 = 16 * R * (t % tp);
                 A acc[R][R];
                 acc_zero<double, R, R>(acc);
@@ -659,6 +768,17 @@ __global__ void k_set_refine_info(bds_info* info, int iters, int converged)
 
 static inline unsigned grid_waves(int64_t units) { return (unsigned)((units + 3) / 4); }
 
+// Register-tile bound NT (np = 16 nt, nt <= NT) of the block factorisation kernels.
+template <int NT> struct NtTag { static constexpr int value = NT; };
+template <typename F> static hipError_t dispatch_nt(int np_max, F&& f)
+{
+    const int nt = np_max / 16;
+    if (nt <= 2) return f(NtTag<2>{});
+    if (nt <= 4) return f(NtTag<4>{});
+    if (nt <= 8) return f(NtTag<8>{});
+    return f(NtTag<16>{});
+}
+
 template <typename C, typename In>
 hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                const FacLv<typename Stor<C>::type, In>* tab, const int64_t* sd,
@@ -668,21 +788,61 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
     const bool r2 = (np_max % 32 == 0);
     if (!tab) {
         One<FacLv<typename Stor<C>::type, In>> o{one, td};
-        if (td > 0) BDS_TIMED("fac_diag", st, k_fac_diag<C, In><<<(unsigned)td, 256, 0, st>>>(o));
-        o.total = tc;
-        if (tc > 0) {
-            if (r2) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(o));
-            else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(o));
+        if (td > 0) {
+            const hipError_t e = dispatch_nt(one.np, [&](auto nt) {
+                constexpr int NT = decltype(nt)::value;
+                BDS_TIMED("fac_diag", st,
+                          k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(o));
+                return hipGetLastError();
+            });
+            if (e != hipSuccess) return e;
         }
-        o.total = ts;
-        if (ts > 0) {
-            if (r2) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(o));
-            else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(o));
+        const int M = one.M, np = one.np;
+        if (np % 64 == 0) {
+            // work-group tile products: 128-wide macro tiles where they fit, 64-wide
+            // lower tiles for the symmetric diagonal blocks
+            auto run = [&](auto mt_c, auto mtd_c) {
+                constexpr int MT = decltype(mt_c)::value, MTD = decltype(mtd_c)::value;
+                o.total = units_fac_couple_wg(M, np, MT);
+                if (o.total > 0)
+                    BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, MT><<<(unsigned)o.total, 256, 0, st>>>(o));
+                o.total = units_fac_schur_wg(M, np, MTD, true);
+                if (o.total > 0)
+                    BDS_TIMED("fac_schur", st,
+                              k_fac_schur_wg<C, In, MTD, true><<<(unsigned)o.total, 256, 0, st>>>(o));
+                o.total = units_fac_schur_wg(M, np, MT, false);
+                if (o.total > 0)
+                    BDS_TIMED("fac_schur_off", st,
+                              k_fac_schur_wg<C, In, MT, false><<<(unsigned)o.total, 256, 0, st>>>(o));
+            };
+            if (np % 128 == 0)
+                run(NtTag<128>{}, NtTag<64>{});
+            else
+                run(NtTag<64>{}, NtTag<64>{});
+        } else {
+            o.total = tc;
+            if (tc > 0) {
+                if (r2) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(o));
+                else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(o));
+            }
+            o.total = ts;
+            if (ts > 0) {
+                if (r2) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(o));
+                else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(o));
+            }
         }
     } else {
         // batched: per-record np may differ; 16-row tiles are valid for every np
         Many<FacLv<typename Stor<C>::type, In>> m{tab, sd, K, td};
-        if (td > 0) BDS_TIMED("fac_diag", st, k_fac_diag<C, In><<<(unsigned)td, 256, 0, st>>>(m));
+        if (td > 0) {
+            const hipError_t e = dispatch_nt(np_max, [&](auto nt) {
+                constexpr int NT = decltype(nt)::value;
+                BDS_TIMED("fac_diag", st,
+                          k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(m));
+                return hipGetLastError();
+            });
+            if (e != hipSuccess) return e;
+        }
         m.start = sc;
         m.total = tc;
         if (tc > 0) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(m));
@@ -694,19 +854,28 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
 }
 
 template <typename In>
-hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab, int K, hipStream_t st)
+hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab, int K, int np_max,
+                                hipStream_t st)
 {
     if (!tab) {
         One<CoarseFac<In>> o{one, 1};
-        if (one.np % 32 == 0) BDS_TIMED("coarse_factor", st, k_coarse_factor<In, 2><<<1, 256, 0, st>>>(o));
-        else BDS_TIMED("coarse_factor", st, k_coarse_factor<In, 1><<<1, 256, 0, st>>>(o));
-    } else {
-        // one work-group per record
-        if (K <= 0) return hipSuccess;
-        Many<CoarseFac<In>> m{tab, nullptr, K, K};
-        BDS_TIMED("coarse_factor", st, k_coarse_factor<In, 1><<<(unsigned)K, 256, 0, st>>>(m));
+        return dispatch_nt(one.np, [&](auto nt) {
+            constexpr int NT = decltype(nt)::value;
+            if (one.np % 32 == 0)
+                BDS_TIMED("coarse_factor", st, k_coarse_factor<In, NT, 2><<<1, chol_threads<NT>(), 0, st>>>(o));
+            else
+                BDS_TIMED("coarse_factor", st, k_coarse_factor<In, NT, 1><<<1, chol_threads<NT>(), 0, st>>>(o));
+            return hipGetLastError();
+        });
     }
-    return hipGetLastError();
+    // one work-group per record
+    if (K <= 0) return hipSuccess;
+    Many<CoarseFac<In>> m{tab, nullptr, K, K};
+    return dispatch_nt(np_max, [&](auto nt) {
+        constexpr int NT = decltype(nt)::value;
+        BDS_TIMED("coarse_factor", st, k_coarse_factor<In, NT, 1><<<(unsigned)K, chol_threads<NT>(), 0, st>>>(m));
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
@@ -873,9 +1042,9 @@ BDS_INST_FAC(float, double)
 BDS_INST_FAC(float, float)
 BDS_INST_FAC(bf16x, double)
 BDS_INST_FAC(bf16x, float)
-template hipError_t launch_coarse_factor<double>(const CoarseFac<double>&, const CoarseFac<double>*, int,
+template hipError_t launch_coarse_factor<double>(const CoarseFac<double>&, const CoarseFac<double>*, int, int,
                                                  hipStream_t);
-template hipError_t launch_coarse_factor<float>(const CoarseFac<float>&, const CoarseFac<float>*, int,
+template hipError_t launch_coarse_factor<float>(const CoarseFac<float>&, const CoarseFac<float>*, int, int,
                                                 hipStream_t);
 template hipError_t launch_solve_fwd<double>(const SolLv<double>&, const SolLv<double>*, const int64_t*,
                                              const int64_t*, int, int64_t, int64_t, int, hipStream_t);

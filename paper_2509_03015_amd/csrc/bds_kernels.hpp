@@ -118,7 +118,7 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                int64_t tot_couple, int64_t tot_schur, int np_max, hipStream_t st);
 
 template <typename In>
-hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab_dev, int K,
+hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab_dev, int K, int np_max,
                                 hipStream_t st);
 
 template <typename T>
