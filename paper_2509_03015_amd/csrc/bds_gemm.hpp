@@ -57,8 +57,10 @@ __device__ __forceinline__ void chunk_load(const View<T>& v, int r0, int k, V (&
 #pragma unroll
         for (int q = 0; q < E; ++q) reg[q] = (V)src[q];
     } else {
-        // MT / E threads per k, E consecutive rows each
-        const int kk = t / (MT / E), row = (t % (MT / E)) * E;
+        // 16 consecutive threads take the 16 k of one group of E consecutive rows
+        // (a 64-byte read each), so that their transposed LDS writes below fall
+        // in consecutive banks
+        const int kk = t & 15, row = (t >> 4) * E;
         const T* src = v.p + (int64_t)(k + kk) * v.ld + r0 + row;
 #pragma unroll
         for (int q = 0; q < E; ++q) reg[q] = (V)src[q];
@@ -77,7 +79,7 @@ __device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[Chun
 #pragma unroll
         for (int q = 0; q < E; ++q) dst[row * LD + kk + q] = reg[q];
     } else {
-        const int kk = t / (MT / E), row = (t % (MT / E)) * E;
+        const int kk = t & 15, row = (t >> 4) * E;
 #pragma unroll
         for (int q = 0; q < E; ++q) dst[(row + q) * LD + kk] = reg[q];
     }

@@ -91,10 +91,10 @@ int64_t units_resid(int N, int np, int d, int R) { return (int64_t)N * (np / (16
 // ---------------------------------------------------------------------------
 // factorisation
 
-// Two work-groups per CU for blocks up to 128 (three waves per SIMD).
+// Two work-groups per CU for blocks up to 128 (two waves per SIMD).
 template <typename C, typename In, int NT, typename Tab>
 __global__ __launch_bounds__(chol_threads<NT>())
-__attribute__((amdgpu_waves_per_eu(NT <= 8 ? 3 : 1))) void k_fac_diag(Tab tab)
+__attribute__((amdgpu_waves_per_eu(NT <= 8 ? 2 : 1))) void k_fac_diag(Tab tab)
 {
     using T = typename Stor<C>::type;
     __shared__ CholSmem<T, NT> sm;
