@@ -47,7 +47,10 @@ WORKLOADS = {
     "f32-k1e2": dict(kind="kalman", N=16384, n=256, d=1, prec="f32", kappa=1e2),
     "f32-k1e4": dict(kind="kalman", N=16384, n=256, d=1, prec="f32", kappa=1e4),
     "f32-k1e6": dict(kind="kalman", N=16384, n=256, d=1, prec="f32", kappa=1e6),
+    "f64-k1e2": dict(kind="kalman", N=16384, n=256, d=1, prec="f64", kappa=1e2),
     "f64-k1e4": dict(kind="kalman", N=16384, n=256, d=1, prec="f64", kappa=1e4),
+    "f64-k1e6": dict(kind="kalman", N=16384, n=256, d=1, prec="f64", kappa=1e6),
+    "bf16-k1e2": dict(kind="kalman", N=16384, n=256, d=1, prec="bf16", kappa=1e2),
 }
 
 
@@ -107,6 +110,11 @@ def kernel_model(N: int, n: int, d: int, nstar: int, esize: int):
     # coarse system, sequential block Cholesky in FP64
     add("coarse_factor", Mc * (7.0 / 3.0) * n ** 3, Mc * 3 * nn * 8)
     add("coarse_solve", Mc * 6.0 * nn * d, Mc * (2 * nn * 8 + 3 * v))
+    # one refinement iteration (mixed precision): FP64 residual R = B - A X over all
+    # block rows (three n x n by n x d products per row; A read once), and the
+    # update X += C with its norms
+    add("residual", N * 6.0 * nn * d, (2 * N - 1) * nn * 8 + 3 * N * v)
+    add("axpy_norm", N * 4.0 * n * d, 3 * N * v)
     return f, b
 
 
@@ -249,12 +257,15 @@ def main():
     X = X_t.cpu().numpy()
     relerr = float(np.linalg.norm(X - Xt) / np.linalg.norm(Xt))
 
-    esize = {"f64": 8, "f32": 4, "bf16": 2}[w["prec"]]
+    # factor storage: FP64, or FP32 for both low-precision modes (BF16 rounds the
+    # MFMA operands, the factor stays in FP32)
+    esize = 8 if w["prec"] == "f64" else 4
     nstar_eff = args.nstar if args.nstar > 0 else 1
     flops, bytes_ = kernel_model(N, n, d, nstar_eff, esize)
     iters = max(int(info.get("iters", 0)), 0)
     tot_flops = sum(flops[k] for k in flops if k.startswith("fac") or k == "coarse_factor") + \
-        (1 + iters) * sum(flops[k] for k in flops if k.startswith("sol") or k == "coarse_solve")
+        (1 + iters) * sum(flops[k] for k in flops if k.startswith("sol") or k == "coarse_solve") + \
+        iters * (flops["residual"] + flops["axpy_norm"])
 
     roof = None
     kernels = {}
@@ -267,11 +278,16 @@ def main():
         per_step_launches = cnt / args.steps
         avg_ms = ms / cnt
         bound = KERNEL_BOUND[dom]
-        solve_mult = (1 + iters) if dom.startswith("sol") or dom == "coarse_solve" else 1
+        if dom.startswith("sol") or dom == "coarse_solve":
+            solve_mult = 1 + iters          # the first solve and one per refinement iteration
+        elif dom in ("residual", "axpy_norm"):
+            solve_mult = iters
+        else:
+            solve_mult = 1
         if bound == "mfma":
             alg = flops[dom] * solve_mult / (per_step_launches)
             achieved = alg / (avg_ms * 1e-3) / 1e12
-            peak = PEAK["mfma_" + ("f64" if esize == 8 else "f32")]
+            peak = PEAK["mfma_" + w["prec"]]
             unit = "TFLOP/s"
         else:
             alg = bytes_[dom] * solve_mult / per_step_launches

@@ -85,14 +85,18 @@ __device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[Chun
     }
 }
 
-// Accumulate the terms into acc (wave (wm, wn) of the 2 x 2 arrangement owns
-// rows wm * MT/2 .. and columns wn * MT/2 .. of the tile).  wave_kend is the
-// k from which the wave's own products in term 0 are known to vanish (a
-// triangular operand); those chunks are still loaded for the other waves.
+// Triangular structure of term 0 that lets whole 16 x 16 output tiles skip
+// a chunk: A lower triangular (row m needs k <= m), or B^T lower triangular
+// (column n needs k <= n).
+enum { TRI_NONE = 0, TRI_A_ROWS = 1, TRI_B_COLS = 2 };
+
+// Accumulate the terms into acc.  Wave (wm, wn) of the 2 x 2 arrangement owns
+// the interleaved 16-row tiles wm, wm + 2, ... and 16-column tiles wn, wn + 2,
+// ... of the MT x MT tile, so that triangular skipping (tri, term 0 only)
+// spreads evenly over the waves.
 template <typename C, int MT, int NTERM, typename TA, typename TB>
 __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT / 32][MT / 32],
-                                                const Term<TA, TB> (&terms)[NTERM], int m0, int n0,
-                                                int wave_kend,
+                                                const Term<TA, TB> (&terms)[NTERM], int m0, int n0, int tri,
                                                 GemmSmem<typename Stor<C>::type, MT>& sm)
 {
     using V = typename Stor<C>::type;
@@ -141,39 +145,45 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
         }
         int tc, kcur;
         locate(c, tc, kcur);
-        if (!(tc == 0 && kcur >= wave_kend)) {
-            const V* As = sm.a[c & 1] + (wm * (MT / 2) + i) * LD + 4 * g;
-            const V* Bs = sm.b[c & 1] + (wn * (MT / 2) + i) * LD + 4 * g;
-            if constexpr (std::is_same<C, bf16x>::value) {
-                V a[R][4], b[R][4];
+        // tile (ta, tb) takes part in this chunk unless term 0's triangle rules it out
+        auto active = [&](int ta, int tb) {
+            if (tc != 0 || tri == TRI_NONE) return true;
+            if (tri == TRI_A_ROWS) return kcur < m0 + 16 * (wm + 2 * ta + 1);
+            return kcur < n0 + 16 * (wn + 2 * tb + 1);
+        };
+        const V* As = sm.a[c & 1] + (16 * wm + i) * LD + 4 * g;
+        const V* Bs = sm.b[c & 1] + (16 * wn + i) * LD + 4 * g;
+        if constexpr (std::is_same<C, bf16x>::value) {
+            V a[R][4], b[R][4];
 #pragma unroll
-                for (int ta = 0; ta < R; ++ta) ld4(As + 16 * ta * LD, a[ta]);
+            for (int ta = 0; ta < R; ++ta) ld4(As + 32 * ta * LD, a[ta]);
 #pragma unroll
-                for (int tb = 0; tb < R; ++tb) ld4(Bs + 16 * tb * LD, b[tb]);
+            for (int tb = 0; tb < R; ++tb) ld4(Bs + 32 * tb * LD, b[tb]);
+#pragma unroll
+            for (int ta = 0; ta < R; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < R; ++tb)
+                    if (active(ta, tb)) tile_mac<C>(acc[ta][tb], a[ta], b[tb]);
+        } else {
+            // two k-steps at a time keeps the operand registers at 4 R
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                V a[R][2], b[R][2];
 #pragma unroll
                 for (int ta = 0; ta < R; ++ta)
 #pragma unroll
-                    for (int tb = 0; tb < R; ++tb) tile_mac<C>(acc[ta][tb], a[ta], b[tb]);
-            } else {
-                // two k-steps at a time keeps the operand registers at 4 R
+                    for (int q = 0; q < 2; ++q) a[ta][q] = As[32 * ta * LD + 2 * h + q];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    V a[R][2], b[R][2];
+                for (int tb = 0; tb < R; ++tb)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) b[tb][q] = Bs[32 * tb * LD + 2 * h + q];
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int ta = 0; ta < R; ++ta)
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) a[ta][q] = As[16 * ta * LD + 2 * h + q];
-#pragma unroll
-                    for (int tb = 0; tb < R; ++tb)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q) b[tb][q] = Bs[16 * tb * LD + 2 * h + q];
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-#pragma unroll
-                        for (int ta = 0; ta < R; ++ta)
-#pragma unroll
-                            for (int tb = 0; tb < R; ++tb) acc[ta][tb] = mma(a[ta][q], b[tb][q], acc[ta][tb]);
-                }
+                        for (int tb = 0; tb < R; ++tb)
+                            if (active(ta, tb)) acc[ta][tb] = mma(a[ta][q], b[tb][q], acc[ta][tb]);
             }
         }
         if (c + 1 < nch) {
@@ -184,14 +194,22 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
     }
 }
 
-// Visit every element of the work-group tile owned by the calling wave.
+// Visit every element of the work-group tile owned by the calling wave:
+// f(row, col, value) with the interleaved tile ownership of wg_tile_product.
 template <typename C, int MT, typename F>
 __device__ __forceinline__ void wg_tile_foreach(const typename AccT<C>::type (&acc)[MT / 32][MT / 32], int m0,
                                                 int n0, F f)
 {
     constexpr int R = MT / 32;
     const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
-    acc_foreach<C, R, R>(acc, m0 + wm * (MT / 2), n0 + wn * (MT / 2), f);
+    const int l = lane_id(), i = l & 15, g = l >> 4;
+#pragma unroll
+    for (int ta = 0; ta < R; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < R; ++tb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                f(m0 + 16 * (wm + 2 * ta) + acc_row<C>(g, r), n0 + 16 * (wn + 2 * tb) + i, acc[ta][tb][r]);
 }
 
 // Map the launch's block index to a work index so that consecutive work

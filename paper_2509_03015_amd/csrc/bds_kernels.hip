@@ -210,7 +210,7 @@ int64_t units_fac_schur_wg(int M, int np, int MT, bool diag)
 }
 
 template <typename C, typename In, int MT, typename Tab>
-__global__ __launch_bounds__(256) void k_fac_couple_wg(Tab tab)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fac_couple_wg(Tab tab)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
@@ -228,7 +228,6 @@ __global__ __launch_bounds__(256) void k_fac_couple_wg(Tab tab)
     const int m0 = MT * (t / tp), n0 = MT * (t % tp);
     const int64_t i = 2 * e + 1;
     if (which == 1 && i + 1 >= s.M) return;
-    const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
     const T* Li = s.Li + e * nn;
     Acc acc[R][R];
     acc_zero<C, R, R>(acc);
@@ -236,19 +235,19 @@ __global__ __launch_bounds__(256) void k_fac_couple_wg(Tab tab)
     if (which == 0) {
         // Wl = Li A[i,i-1]: Li is lower triangular, so k < m0 + MT
         const Term<T, In> terms[1] = {{{Li, np, true}, {s.As + (i - 1) * nn, np, false}, 0, min(np, m0 + MT)}};
-        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, m0 + (wm + 1) * (MT / 2), sm);
+        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, TRI_A_ROWS, sm);
         out = s.Wl + e * nn;
     } else {
         // Pr = A[i+1,i] Li^T: k < n0 + MT
         const Term<In, T> terms[1] = {{{s.As + i * nn, np, true}, {Li, np, true}, 0, min(np, n0 + MT)}};
-        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, n0 + (wn + 1) * (MT / 2), sm);
+        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, TRI_B_COLS, sm);
         out = s.Pr + e * nn;
     }
     wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
 }
 
 template <typename C, typename In, int MT, bool DIAG, typename Tab>
-__global__ __launch_bounds__(256) void k_fac_schur_wg(Tab tab)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fac_schur_wg(Tab tab)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
@@ -276,7 +275,7 @@ __global__ __launch_bounds__(256) void k_fac_schur_wg(Tab tab)
         const T* W = right ? s.Wl + j * nn : s.Wl;
         const Term<T, T> terms[2] = {{{P, np, true}, {P, np, true}, 0, left ? np : 0},
                                      {{W, np, false}, {W, np, false}, 0, right ? np : 0}};
-        wg_tile_product<C, MT, 2>(acc, terms, m0, n0, np, sm);
+        wg_tile_product<C, MT, 2>(acc, terms, m0, n0, TRI_NONE, sm);
         const In* a = s.Ad + 2 * j * nn;
         T* out = s.Adn + j * nn;
         wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) {
@@ -290,7 +289,7 @@ __global__ __launch_bounds__(256) void k_fac_schur_wg(Tab tab)
         const T* P = s.Pr + j * nn;
         const T* W = s.Wl + j * nn;
         const Term<T, T> terms[1] = {{{P, np, true}, {W, np, false}, 0, np}};
-        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, np, sm);
+        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, TRI_NONE, sm);
         T* out = s.Asn + j * nn;
         wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
     }
