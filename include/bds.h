@@ -83,7 +83,9 @@ typedef struct bds_desc {
                            (the paper's crossover N_star); 0 = library choice */
     int32_t max_refine; /* refinement iteration cap for prec != BDS_F64; 0 = default (30) */
     int32_t reserved;   /* must be 0 */
-    double refine_tol;  /* stop when ||dX||_F <= refine_tol * ||X||_F; 0 = default (1e-14) */
+    double refine_tol;  /* stop when the estimated remaining error is <= refine_tol * ||X||_F:
+                           ||dX||_F itself, or rho * ||dX||_F once the contraction rho of
+                           successive corrections is known; 0 = default (1e-14) */
 } bds_desc;
 
 /* Device-side outcome record, written by the kernels (8 x int32). */

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/bds.h"
+#include "bds_graph.hpp"
 #include "bds_host.hpp"
 #include "bds_kernels.hpp"
 #include "bds_plan.hpp"
@@ -276,9 +277,18 @@ int bds_factor(const bds_desc* desc, const double* Ad, const double* As, void* f
     const SysPlan p = make_plan(*desc);
     if (factor_bytes < p.factor_bytes) return BDS_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (p.prec == BDS_F64) return factor_impl<double>(p, Ad, As, factor_ws, info, st);
-    if (p.prec == BDS_BF16) return factor_impl<bf16x>(p, Ad, As, factor_ws, info, st);
-    return factor_impl<float>(p, Ad, As, factor_ws, info, st);
+    GraphKey key;
+    key.kind = 1;
+    key.add_desc(*desc);
+    key.add(Ad);
+    key.add(As);
+    key.add(factor_ws);
+    key.add(info);
+    return run_graph(key, st, [&](hipStream_t s) {
+        if (p.prec == BDS_F64) return factor_impl<double>(p, Ad, As, factor_ws, info, s);
+        if (p.prec == BDS_BF16) return factor_impl<bf16x>(p, Ad, As, factor_ws, info, s);
+        return factor_impl<float>(p, Ad, As, factor_ws, info, s);
+    });
 }
 
 int bds_solve(const bds_desc* desc, const void* factor_ws, size_t factor_bytes, const double* Ad, const double* As,
@@ -291,7 +301,21 @@ int bds_solve(const bds_desc* desc, const void* factor_ws, size_t factor_bytes, 
     const SysPlan p = make_plan(*desc);
     if (factor_bytes < p.factor_bytes || solve_bytes < p.solve_bytes) return BDS_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (p.prec == BDS_F64) return solve_impl<double>(p, factor_ws, Ad, As, B, X, solve_ws, info, st);
+    if (p.prec == BDS_F64) {
+        // a fixed launch sequence: replayed as a graph
+        GraphKey key;
+        key.kind = 2;
+        key.add_desc(*desc);
+        key.add(factor_ws);
+        key.add(B);
+        key.add(X);
+        key.add(solve_ws);
+        key.add(info);
+        return run_graph(key, st, [&](hipStream_t s) {
+            return solve_impl<double>(p, factor_ws, Ad, As, B, X, solve_ws, info, s);
+        });
+    }
+    // refinement synchronises once per iteration to test its stopping rule
     return solve_impl<float>(p, factor_ws, Ad, As, B, X, solve_ws, info, st);
 }
 

@@ -6,6 +6,7 @@
 #include <cstddef>
 
 #include "bds_plan.hpp"
+#include "bds_refine.hpp"
 
 #define BDS_TRY(...)                           \
     do {                                       \
@@ -29,28 +30,5 @@ struct Level0 {
 };
 
 Level0 level0_matrices(const SysPlan& p, const double* Ad, const double* As, const void* fws);
-
-// Stopping rule of the iterative refinement, given the norms of the latest
-// correction (cn) and of the updated solution (xn), both Frobenius.  Returns
-// true when the iteration should stop and sets `converged`:
-//   cn <= tol * xn                  -> converged
-//   NaN                             -> diverged
-//   cn > prev / 2 (not contracting) -> stop; converged iff cn <= 1e-8 * xn
-// prev carries the previous correction norm (start with HUGE_VAL).
-inline bool refine_stop(double cn, double xn, double& prev, double tol, int& converged)
-{
-    converged = 0;
-    if (!(cn == cn) || !(xn == xn)) return true;
-    if (cn <= tol * xn) {
-        converged = 1;
-        return true;
-    }
-    if (cn > 0.5 * prev) {
-        converged = cn <= 1e-8 * xn;
-        return true;
-    }
-    prev = cn;
-    return false;
-}
 
 }  // namespace bds
