@@ -53,6 +53,14 @@ WORKLOADS = {
     "f64-k1e4": dict(kind="kalman", N=16384, n=256, d=1, prec="f64", kappa=1e4),
     "f64-k1e6": dict(kind="kalman", N=16384, n=256, d=1, prec="f64", kappa=1e6),
     "bf16-k1e2": dict(kind="kalman", N=16384, n=256, d=1, prec="bf16", kappa=1e2, refine_tol=1e-11),
+    # the small case: N=64, n=16, d=1, plain FP64 (latency-bound)
+    "tiny": dict(kind="dd", N=64, n=16, d=1, prec="f64"),
+    # many uneven systems, one launch per kernel and level: K=512, N~U{32..2048},
+    # n in {8,16,32,64}, d in {1,4}; one step factorises and solves all of them
+    "batched": dict(kind="batched", K=512, prec="f64"),
+    "batched-f32": dict(kind="batched", K=512, prec="f32", refine_tol=1e-11),
+    # differentiation: factor + solve + adjoint (dA, dB of sum(W*X)), Kalman kappa~1e4
+    "adjoint": dict(kind="kalman", N=4096, n=32, d=4, prec="f64", kappa=1e4, adjoint=True),
 }
 
 
@@ -155,23 +163,70 @@ def make_inputs(w: dict, seed: int = 0):
     return inputs.gen_kalman(w["N"], w["n"], w["d"], rho, seed=seed)
 
 
-def cpu_baseline(Ad, As, B, budget_s: float = 15.0):
-    """Oracle factor + solve on the leading sub-chain of Ns blocks, scaled to the full N."""
+def cpu_baseline(Ad, As, B, budget_s: float = 15.0, adjoint: bool = False):
+    """Oracle factor + solve (+ adjoint) on the leading sub-chain of Ns blocks, scaled to the full N."""
     import oracle
     N = Ad.shape[0]
     Ns = min(N, 64)
+    W = np.ones_like(B)
     while True:
         t0 = time.perf_counter()
-        oracle.solve(Ad[:Ns], As[:Ns - 1], B[:Ns])
+        X = oracle.solve(Ad[:Ns], As[:Ns - 1], B[:Ns])
+        if adjoint:
+            oracle.backward(Ad[:Ns], As[:Ns - 1], X, W[:Ns])
         dt = time.perf_counter() - t0
         if Ns >= N or dt * 2 > budget_s / 2:
             break
         Ns = min(N, Ns * 2)
-    per_block = dt / Ns
-    full_s = per_block * N
+    full_s = dt / Ns * N
+    what = "factor + solve + adjoint" if adjoint else "factor + solve"
     return {"value": 1.0 / full_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 block-Cholesky factor + solve of the leading {Ns} of {N} blocks "
+            "sample": f"FP64 block-Cholesky {what} of the leading {Ns} of {N} blocks "
                       f"({dt:.2f} s, one thread), scaled by {N / Ns:g} to the full chain"}
+
+
+def cpu_baseline_batched(systems, budget_s: float = 15.0):
+    """Oracle on the first systems of the batch (OpenMP over systems), scaled to the whole batch."""
+    import oracle
+    K = len(systems)
+    work = [s[0].shape[0] * s[0].shape[1] ** 3 for s in systems]
+    k = min(K, 8)
+    while True:
+        t0 = time.perf_counter()
+        _, used = oracle.solve_batched([(s[0], s[1], s[3]) for s in systems[:k]])
+        dt = time.perf_counter() - t0
+        if k >= K or dt * 2 > budget_s / 2:
+            break
+        k = min(K, k * 2)
+    scale = sum(work) / sum(work[:k])
+    return {"value": K / (dt * scale), "unit": "solves/s", "cores": int(used), "kind": "oracle",
+            "sample": f"FP64 block-Cholesky factor + solve of the first {k} of {K} systems ({dt:.2f} s, "
+                      f"{used} threads over systems), scaled by the work ratio {scale:.2f} (sum of N n^3)"}
+
+
+def merged_model(models, names):
+    """Sum per-system kernel models; fold fac_schur_off into fac_schur where the trace has no
+    separate off-diagonal Schur launch (per-wave kernels, batched form)."""
+    f, b = {}, {}
+    for mf, mb in models:
+        for k in mf:
+            key = "fac_schur" if (k == "fac_schur_off" and "fac_schur_off" not in names) else k
+            f[key] = f.get(key, 0.0) + mf[k]
+            b[key] = b.get(key, 0.0) + mb[k]
+    return f, b
+
+
+def timed_steps(torch, stream, step, steps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, time.perf_counter() - t0
 
 
 def main():
@@ -194,7 +249,7 @@ def main():
 
     import torch
     from paper_2509_03015_amd import _binding as bb
-    from paper_2509_03015_amd import solver
+    from paper_2509_03015_amd import inputs, solver
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -211,78 +266,104 @@ def main():
         return
 
     w = WORKLOADS[args.workload]
-    N, n, d = w["N"], w["n"], w["d"]
-    t_gen = time.perf_counter()
-    Ad, As, Xt, B = make_inputs(w)
-    t_gen = time.perf_counter() - t_gen
-    print(f"[bench] workload {args.workload}: N={N} n={n} d={d} prec={w['prec']} "
-          f"(inputs {t_gen:.1f} s)", file=sys.stderr, flush=True)
-
-    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    Ad_t, As_t, B_t = to(Ad), to(As), to(B)
-    X_t = torch.empty_like(B_t)
-
-    t_init = time.perf_counter()
+    kind = w["kind"]
+    prec = w["prec"]
     tol = w.get("refine_tol", 0.0)
-    F = solver.factor(Ad_t, As_t, prec=w["prec"], nstar=args.nstar)
-    F.solve(B_t, out=X_t, refine_tol=tol)
-    torch.cuda.synchronize()
-    t_init = time.perf_counter() - t_init
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    t_gen = time.perf_counter()
+    nstar_eff = args.nstar if args.nstar > 0 else 1
+    esize = 8 if prec == "f64" else 4  # factor storage: FP64, else FP32 (BF16 rounds MFMA operands only)
+
+    if kind == "batched":
+        systems = inputs.gen_batched(w["K"], seed=0)
+        t_gen = time.perf_counter() - t_gen
+        Ads = [to(s[0]) for s in systems]
+        Ass = [to(s[1]) if s[0].shape[0] > 1 else None for s in systems]
+        Bs = [to(s[3]) for s in systems]
+        Xs = [torch.empty_like(B) for B in Bs]
+        t_init = time.perf_counter()
+        F = solver.factor_batched(Ads, Ass, prec=prec, nstar=args.nstar)
+        F.solve(Bs, outs=Xs, refine_tol=tol)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t_init
+
+        def step():
+            F.refactor()
+            F.solve(Bs, outs=Xs, refine_tol=tol, check=False)
+
+        def result_error():
+            errs = [float(np.linalg.norm(X.cpu().numpy() - s[2]) / np.linalg.norm(s[2])) for X, s in zip(Xs, systems)]
+            return max(errs)
+
+        def info_iters():
+            return max(int(r["iters"]) for r in F.check("bench"))
+
+        shapes = [(s[0].shape[0], s[0].shape[1], s[3].shape[2]) for s in systems]
+        per_step = len(systems)
+        config = {"workload": args.workload, "K": len(systems), "N": "U{32..2048}", "n": "{8,16,32,64}",
+                  "d": "{1,4}", "prec": prec, "generator": "dd", "nstar": nstar_eff}
+    else:
+        N, n, d = w["N"], w["n"], w["d"]
+        Ad, As, Xt, B = make_inputs(w)
+        t_gen = time.perf_counter() - t_gen
+        Ad_t, As_t, B_t = to(Ad), to(As), to(B)
+        X_t = torch.empty_like(B_t)
+        adjoint = w.get("adjoint", False)
+        Wt = to(np.random.default_rng(11).standard_normal(B.shape)) if adjoint else None
+        t_init = time.perf_counter()
+        F = solver.factor(Ad_t, As_t, prec=prec, nstar=args.nstar)
+        F.solve(B_t, out=X_t, refine_tol=tol)
+        if adjoint:
+            F.backward(X_t, Wt)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t_init
+
+        def step():
+            F.refactor()
+            F.solve(B_t, out=X_t, refine_tol=tol, check=False)
+            if adjoint:
+                F.backward(X_t, Wt, check=False)
+
+        def result_error():
+            X = X_t.cpu().numpy()
+            return float(np.linalg.norm(X - Xt) / np.linalg.norm(Xt))
+
+        def info_iters():
+            return max(int(F.check("bench").get("iters", 0)), 0)
+
+        shapes = [(N, n, d)]
+        per_step = 1
+        config = {"workload": args.workload, "N": N, "n": n, "d": d, "prec": prec, "generator": kind,
+                  **({"kappa": w["kappa"]} if "kappa" in w else {}), "nstar": nstar_eff,
+                  **({"adjoint": True} if adjoint else {})}
+    print(f"[bench] workload {args.workload} ({prec}): inputs {t_gen:.1f} s, init {t_init:.2f} s",
+          file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
-        F.refactor()
-        F.solve(B_t, out=X_t, refine_tol=tol, check=False)
+        step()
     torch.cuda.synchronize()
-    print(f"[bench] warmup done", file=sys.stderr, flush=True)
+    print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    # timed region: the library's own launch path (graph replay where it applies),
-    # bracketed by device synchronisation
+    # timed region: the library's own launch path (graph replay where it applies)
     stream = torch.cuda.current_stream(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        F.refactor()
-        F.solve(B_t, out=X_t, refine_tol=tol, check=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    info = F.check("bench")
-    ms_step = ms_total / args.steps
+    ms_step, wall = timed_steps(torch, stream, step, args.steps)
+    iters = info_iters() if prec != "f64" else 0
 
     # per-kernel durations (HIP events around every launch, which also makes the
     # library launch kernel by kernel) over a second run of the same steps
-    trace = not args.no_trace
-    kern, dropped = {}, 0
-    if trace:
-        bb.trace_enable(args.steps * 4096)
-        torch.cuda.synchronize()
-        e2 = torch.cuda.Event(enable_timing=True)
-        e3 = torch.cuda.Event(enable_timing=True)
-        e2.record(stream)
-        for _ in range(args.steps):
-            F.refactor()
-            F.solve(B_t, out=X_t, refine_tol=tol, check=False)
-        e3.record(stream)
-        torch.cuda.synchronize()
-        ms_step_traced = e2.elapsed_time(e3) / args.steps
+    kern, dropped, ms_step_traced = {}, 0, None
+    if not args.no_trace:
+        bb.trace_enable(args.steps * 65536 if kind == "batched" else args.steps * 4096)
+        ms_step_traced, _ = timed_steps(torch, stream, step, args.steps)
         kern, dropped = bb.trace_read()
         bb.trace_enable(0)
+    err = result_error()
 
-    X = X_t.cpu().numpy()
-    relerr = float(np.linalg.norm(X - Xt) / np.linalg.norm(Xt))
-
-    # factor storage: FP64, or FP32 for both low-precision modes (BF16 rounds the
-    # MFMA operands, the factor stays in FP32)
-    esize = 8 if w["prec"] == "f64" else 4
-    nstar_eff = args.nstar if args.nstar > 0 else 1
-    flops, bytes_ = kernel_model(N, n, d, nstar_eff, esize)
-    iters = max(int(info.get("iters", 0)), 0)
+    flops, bytes_ = merged_model([kernel_model(N_, n_, d_, nstar_eff, esize) for N_, n_, d_ in shapes], set(kern))
+    adj = config.get("adjoint", False)
+    solves = 1 + iters + (1 if adj else 0)   # the adjoint solves once more with the factor
     tot_flops = sum(flops[k] for k in flops if k.startswith("fac") or k == "coarse_factor") + \
-        (1 + iters) * sum(flops[k] for k in flops if k.startswith("sol") or k == "coarse_solve") + \
+        solves * sum(flops[k] for k in flops if k.startswith("sol") or k == "coarse_solve") + \
         iters * (flops["residual"] + flops["axpy_norm"])
 
     roof = None
@@ -297,18 +378,18 @@ def main():
         avg_ms = ms / cnt
         bound = KERNEL_BOUND[dom]
         if dom.startswith("sol") or dom == "coarse_solve":
-            solve_mult = 1 + iters          # the first solve and one per refinement iteration
+            mult = solves          # the first solve, one per refinement iteration, the adjoint's
         elif dom in ("residual", "axpy_norm"):
-            solve_mult = iters
+            mult = iters
         else:
-            solve_mult = 1
+            mult = 1
         if bound == "mfma":
-            alg = flops[dom] * solve_mult / (per_step_launches)
+            alg = flops[dom] * mult / per_step_launches
             achieved = alg / (avg_ms * 1e-3) / 1e12
-            peak = PEAK["mfma_" + w["prec"]]
+            peak = PEAK["mfma_" + prec]
             unit = "TFLOP/s"
         else:
-            alg = bytes_[dom] * solve_mult / per_step_launches
+            alg = bytes_[dom] * mult / per_step_launches
             achieved = alg / (avg_ms * 1e-3) / 1e9
             peak = PEAK["hbm"]
             unit = "GB/s"
@@ -319,7 +400,7 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": 1000.0 / ms_step,
+        "value": per_step * 1000.0 / ms_step,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -328,24 +409,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": w["prec"],
+        "dtype": prec,
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": N, "n": n, "d": d, "prec": w["prec"],
-                   "generator": w["kind"], **({"kappa": w["kappa"]} if "kappa" in w else {}),
-                   "nstar": nstar_eff},
+        "config": config,
         "tflops": tot_flops / (ms_step * 1e-3) / 1e12,
-        "relerr_vs_manufactured": relerr,
-        "refine_iters": iters if w["prec"] != "f64" else 0,
+        "relerr_vs_manufactured": err,
+        "refine_iters": iters,
         "wall_s_timed": wall,
         "init_s": t_init,
         "roofline": roof,
         "kernels": kernels,
-        "ms_per_step_kernel_by_kernel": ms_step_traced if trace else None,
+        "ms_per_step_kernel_by_kernel": ms_step_traced,
         "trace_dropped": dropped,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(Ad, As, B)
+        if kind == "batched":
+            out["cpu_baseline"] = cpu_baseline_batched(systems)
+        else:
+            out["cpu_baseline"] = cpu_baseline(Ad, As, B, adjoint=adj)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
