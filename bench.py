@@ -128,10 +128,9 @@ def kernel_model(N: int, n: int, d: int, nstar: int, esize: int):
     return f, b
 
 
-KERNEL_BOUND = {"fac_diag": "mfma", "fac_couple": "mfma", "fac_schur": "mfma", "fac_schur_off": "mfma",
-                "coarse_factor": "mfma",
-                "sol_fwd_int": "hbm", "sol_fwd_sep": "hbm", "sol_bwd": "hbm", "coarse_solve": "hbm",
-                "residual": "hbm", "axpy_norm": "hbm"}
+# kernels with an algorithmic model (candidates for the roofline entry)
+MODELLED_KERNELS = ("fac_diag", "fac_couple", "fac_schur", "fac_schur_off", "coarse_factor", "sol_fwd_int",
+                "sol_fwd_sep", "sol_bwd", "coarse_solve", "residual", "axpy_norm")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_03015_amd", "csrc", "bds_kernels.hip")
 
 
@@ -371,32 +370,37 @@ def main():
     if kern:
         for k, (cnt, ms) in kern.items():
             kernels[k] = {"launches_per_step": cnt / args.steps, "ms_per_step": ms / args.steps}
-        timed = {k: v for k, v in kern.items() if k in KERNEL_BOUND}
+        timed = {k: v for k, v in kern.items() if k in MODELLED_KERNELS}
         dom = max(timed, key=lambda k: timed[k][1])
         cnt, ms = timed[dom]
         per_step_launches = cnt / args.steps
         avg_ms = ms / cnt
-        bound = KERNEL_BOUND[dom]
         if dom.startswith("sol") or dom == "coarse_solve":
             mult = solves          # the first solve, one per refinement iteration, the adjoint's
         elif dom in ("residual", "axpy_norm"):
             mult = iters
         else:
             mult = 1
+        # the kernel's roofline: MFMA-bound when its arithmetic intensity (algorithmic
+        # flops per algorithmic HBM byte) reaches the ridge point peak_flops / peak_bw
+        fl = flops[dom] * mult / per_step_launches
+        by = bytes_[dom] * mult / per_step_launches
+        peak_f, peak_b = PEAK["mfma_" + prec], PEAK["hbm"]
+        ridge = peak_f * 1e12 / (peak_b * 1e9)
+        bound = "mfma" if by == 0 or fl / by >= ridge else "hbm"
         if bound == "mfma":
-            alg = flops[dom] * mult / per_step_launches
+            alg, peak, unit = fl, peak_f, "TFLOP/s"
             achieved = alg / (avg_ms * 1e-3) / 1e12
-            peak = PEAK["mfma_" + prec]
-            unit = "TFLOP/s"
         else:
-            alg = bytes_[dom] * mult / per_step_launches
+            alg, peak, unit = by, peak_b, "GB/s"
             achieved = alg / (avg_ms * 1e-3) / 1e9
-            peak = PEAK["hbm"]
-            unit = "GB/s"
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                 "traffic": measured_traffic(dom, args.workload), "kernel": dom,
                 "avg_launch_ms": avg_ms, "launches_per_step": per_step_launches,
-                "algorithmic_per_launch": alg, "share_of_step": (ms / args.steps) / ms_step_traced}
+                "algorithmic_per_launch": alg, "flops_per_launch": fl, "bytes_per_launch": by,
+                "arith_intensity": fl / by if by else None, "ridge": ridge,
+                "tflops": fl / (avg_ms * 1e-3) / 1e12, "gbps": by / (avg_ms * 1e-3) / 1e9,
+                "share_of_step": (ms / args.steps) / ms_step_traced}
 
     out = {
         "metric": METRIC,

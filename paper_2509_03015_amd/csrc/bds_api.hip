@@ -59,7 +59,7 @@ SysPlan make_plan(const bds_desc& d, size_t base_f, size_t base_s)
         L.E = M / 2;
         L.Mn = (M + 1) / 2;
         L.Li = take(f, (size_t)L.E * blk * p.esize);
-        L.Wl = take(f, (size_t)L.E * blk * p.esize);
+        L.Wt = take(f, (size_t)L.E * blk * p.esize);
         L.Pr = take(f, (size_t)L.E * blk * p.esize);
         L.Adn = take(f, (size_t)L.Mn * blk * p.esize);
         L.Asn = take(f, (size_t)std::max<int64_t>(L.Mn - 1, 0) * blk * p.esize);
@@ -112,16 +112,16 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
         const LevelPlan& L = p.lv[l];
         const int M = (int)L.M;
         if (l == 0) {
-            FacLv<T, double> r{a0.Ad, a0.As, at<T>(fws, L.Li), at<T>(fws, L.Wl), at<T>(fws, L.Pr),
+            FacLv<T, double> r{a0.Ad, a0.As, at<T>(fws, L.Li), at<T>(fws, L.Wt), at<T>(fws, L.Pr),
                                at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, 0, 0, info};
             BDS_TRY(launch_factor_level<C, double>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                                   units_fac_couple(M, np, tile_r(np)), units_fac_schur(M, np, tile_r(np)), np, st));
+                                                   units_fac_couple(M, np), units_fac_schur(M, np), np, st));
         } else {
             const LevelPlan& P = p.lv[l - 1];
-            FacLv<T, T> r{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<T>(fws, L.Li), at<T>(fws, L.Wl),
+            FacLv<T, T> r{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<T>(fws, L.Li), at<T>(fws, L.Wt),
                           at<T>(fws, L.Pr), at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, (int)l, 0, info};
             BDS_TRY(launch_factor_level<C, T>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                              units_fac_couple(M, np, tile_r(np)), units_fac_schur(M, np, tile_r(np)), np, st));
+                                              units_fac_couple(M, np), units_fac_schur(M, np), np, st));
         }
     }
     const int Lv = (int)p.lv.size();
@@ -149,10 +149,10 @@ int solve_core(const SysPlan& p, const void* fws, void* sws, const double* B0, d
         const LevelPlan& L = p.lv[l];
         const double* B = l == 0 ? B0 : at<double>(sws, p.lv[l - 1].Bn);
         double* X = l == 0 ? X0 : at<double>(sws, p.lv[l - 1].Xn);
-        recs[l] = SolLv<T>{at<T>(fws, L.Li), at<T>(fws, L.Wl), at<T>(fws, L.Pr), B, at<double>(sws, L.Y),
+        recs[l] = SolLv<T>{at<T>(fws, L.Li), at<T>(fws, L.Wt), at<T>(fws, L.Pr), B, at<double>(sws, L.Y),
                            at<double>(sws, L.Bn), at<double>(sws, L.Xn), X, (int)L.M, np, d, 0};
-        BDS_TRY(launch_solve_fwd<T>(recs[l], nullptr, nullptr, nullptr, 1, units_sol_fwd_int((int)L.M, np, d, tile_r(np)),
-                                    units_sol_fwd_sep((int)L.M, np, d, tile_r(np)), np, st));
+        BDS_TRY(launch_solve_fwd<T>(recs[l], nullptr, nullptr, nullptr, 1, units_sol_fwd_int((int)L.M, np, d),
+                                    units_sol_fwd_sep((int)L.M, np, d), np, st));
     }
     CoarseSol c{at<double>(fws, p.Lc), at<double>(fws, p.Lsc),
                 Lv == 0 ? B0 : at<double>(sws, p.lv.back().Bn), at<double>(sws, p.Yc),
@@ -180,7 +180,7 @@ int refined_solve(const SysPlan& p, const void* fws, const Level0& a0, void* sws
     int iters = 0, converged = 0;
     double prev = HUGE_VAL;
     for (int it = 1; it <= p.max_refine; ++it) {
-        BDS_TRY(launch_residual(ra, nullptr, nullptr, 1, units_resid(N, np, d, tile_r(np)), np, st));
+        BDS_TRY(launch_residual(ra, nullptr, nullptr, 1, units_resid(N, np, d), np, st));
         rc = solve_core<T>(p, fws, sws, R, C, st);
         if (rc != BDS_OK) return rc;
         BDS_TRY(launch_axpy_norm(xa, nullptr, nullptr, 1, N, st));

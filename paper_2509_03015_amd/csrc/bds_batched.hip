@@ -35,6 +35,12 @@ struct BatchPlan {
     int prec = BDS_F64;
     int nlev = 0;                 // deepest recursion over the batch
     std::vector<SysPlan> sys;     // offsets relative to the workspace start
+    // systems are grouped by padded block size np (one launch per group, so that
+    // each group runs the tiling of its own np): the distinct np in increasing
+    // order, and the number of systems of each group that reach each level
+    std::vector<int> nps;
+    std::vector<std::vector<int64_t>> lvcnt;   // [level][group]
+    int group(int np) const { return (int)(std::lower_bound(nps.begin(), nps.end(), np) - nps.begin()); }
     size_t ftab = 0, ftab_bytes = 0;   // factor table region
     size_t stab = 0, stab_bytes = 0;   // solve table region (solve core)
     size_t rtab = 0, rtab_bytes = 0;   // refinement / packing table region
@@ -61,35 +67,47 @@ int make_batch_plan(int64_t K, const bds_desc* descs, BatchPlan& bp)
     bp.prec = descs[0].prec;
     bp.sys.reserve((size_t)K);
     size_t f = 0, s = 0;
-    std::vector<int64_t> per_level;
     for (int64_t k = 0; k < K; ++k) {
         SysPlan p = make_plan(descs[k], f, s);
         f += p.factor_bytes;
         s += p.solve_bytes;
         bp.nlev = std::max<int>(bp.nlev, (int)p.lv.size());
-        if (per_level.size() < p.lv.size()) per_level.resize(p.lv.size(), 0);
-        for (size_t l = 0; l < p.lv.size(); ++l) per_level[l] += 1;
+        bp.nps.push_back((int)p.np);
         bp.sys.push_back(std::move(p));
     }
+    std::sort(bp.nps.begin(), bp.nps.end());
+    bp.nps.erase(std::unique(bp.nps.begin(), bp.nps.end()), bp.nps.end());
+    const size_t G = bp.nps.size();
+    bp.lvcnt.assign((size_t)bp.nlev, std::vector<int64_t>(G, 0));
+    std::vector<int64_t> gcnt(G, 0);
+    for (const SysPlan& p : bp.sys) {
+        const int g = bp.group((int)p.np);
+        gcnt[g] += 1;
+        for (size_t l = 0; l < p.lv.size(); ++l) bp.lvcnt[l][g] += 1;
+    }
     const size_t Kz = (size_t)K;
-    // factor tables: per level records + 3 prefix arrays, coarse records (two kinds), packing
+    // factor tables: per level and group records + 3 prefix arrays, coarse records (two kinds), packing
     size_t ft = 0;
-    for (int l = 0; l < bp.nlev; ++l) ft += tab_bytes((size_t)per_level[l], sizeof(FacLv<double, double>), 3);
+    for (int l = 0; l < bp.nlev; ++l)
+        for (size_t g = 0; g < G; ++g)
+            if (bp.lvcnt[l][g] > 0) ft += tab_bytes((size_t)bp.lvcnt[l][g], sizeof(FacLv<double, double>), 3);
     ft += 2 * tab_bytes(Kz, sizeof(CoarseFac<double>), 0);
     ft += tab_bytes(2 * Kz, sizeof(PackRec), 1);
     bp.ftab = f;
     bp.ftab_bytes = align_up(ft);
     bp.factor_bytes = f + bp.ftab_bytes;
-    // solve-core tables: per level records + 3 prefix arrays, coarse records + prefix
+    // solve-core tables: per level and group records + 3 prefix arrays, coarse records + prefix
     size_t st = 0;
-    for (int l = 0; l < bp.nlev; ++l) st += tab_bytes((size_t)per_level[l], sizeof(SolLv<double>), 3);
+    for (int l = 0; l < bp.nlev; ++l)
+        for (size_t g = 0; g < G; ++g)
+            if (bp.lvcnt[l][g] > 0) st += tab_bytes((size_t)bp.lvcnt[l][g], sizeof(SolLv<double>), 3);
     st += tab_bytes(Kz, sizeof(CoarseSol), 1);
     bp.stab = s;
     bp.stab_bytes = align_up(st);
     s += bp.stab_bytes;
-    // refinement and packing tables
-    size_t rt = tab_bytes(Kz, sizeof(ResidArgs), 1) + tab_bytes(Kz, sizeof(AxpyArgs), 1) +
-                tab_bytes(Kz, sizeof(PackRec), 1);
+    // refinement (residual records per group) and packing tables
+    size_t rt = tab_bytes(Kz, sizeof(AxpyArgs), 1) + tab_bytes(Kz, sizeof(PackRec), 1);
+    for (size_t g = 0; g < G; ++g) rt += tab_bytes((size_t)gcnt[g], sizeof(ResidArgs), 1);
     bp.rtab = s;
     bp.rtab_bytes = align_up(rt);
     s += bp.rtab_bytes;
@@ -173,55 +191,58 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
             return BDS_EWORKSPACE;
     }
     struct LevelTab {
+        int level, np;
         const void* recs;
         const int64_t *sd, *sc, *ss;
         int64_t td, tc, ts;
         int cnt;
-        int np_max;
     };
-    std::vector<LevelTab> lt((size_t)bp.nlev);
+    std::vector<LevelTab> lt;
     for (int l = 0; l < bp.nlev; ++l) {
-        std::vector<int> members;
-        for (int k = 0; k < K; ++k)
-            if ((int)bp.sys[k].lv.size() > l) members.push_back(k);
-        LevelTab& L = lt[l];
-        L.cnt = (int)members.size();
-        L.np_max = 16;
-        for (int k : members) L.np_max = std::max<int>(L.np_max, (int)bp.sys[k].np);
-        const size_t m = members.size();
-        // level 0 reads the FP64 inputs (or their padded copies), deeper levels the
-        // previous level's Schur complement in the factor precision T
-        auto fill = [&](auto* h, auto read_ad, auto read_as) {
-            using Rec = std::remove_pointer_t<decltype(h)>;
-            for (size_t i = 0; i < m; ++i) {
-                const int k = members[i];
-                const SysPlan& p = bp.sys[k];
-                const LevelPlan& V = p.lv[l];
-                h[i] = Rec{read_ad(k), read_as(k), at<T>(fws, V.Li), at<T>(fws, V.Wl), at<T>(fws, V.Pr),
-                           at<T>(fws, V.Adn), at<T>(fws, V.Asn), (int)V.M, (int)p.np, l, 0, info + k};
+        for (const int np : bp.nps) {
+            std::vector<int> members;
+            for (int k = 0; k < K; ++k)
+                if ((int)bp.sys[k].lv.size() > l && (int)bp.sys[k].np == np) members.push_back(k);
+            if (members.empty()) continue;
+            lt.push_back(LevelTab{});
+            LevelTab& L = lt.back();
+            L.level = l;
+            L.np = np;
+            L.cnt = (int)members.size();
+            const size_t m = members.size();
+            // level 0 reads the FP64 inputs (or their padded copies), deeper levels the
+            // previous level's Schur complement in the factor precision T
+            auto fill = [&](auto* h, auto read_ad, auto read_as) {
+                using Rec = std::remove_pointer_t<decltype(h)>;
+                for (size_t i = 0; i < m; ++i) {
+                    const int k = members[i];
+                    const SysPlan& p = bp.sys[k];
+                    const LevelPlan& V = p.lv[l];
+                    h[i] = Rec{read_ad(k), read_as(k), at<T>(fws, V.Li), at<T>(fws, V.Wt), at<T>(fws, V.Pr),
+                               at<T>(fws, V.Adn), at<T>(fws, V.Asn), (int)V.M, (int)p.np, l, 0, info + k};
+                }
+            };
+            if (l == 0) {
+                const FacLv<T, double>* dev = nullptr;
+                FacLv<T, double>* h = tab.take<FacLv<T, double>>(m, &dev);
+                if (!h) return BDS_EWORKSPACE;
+                fill(h, [&](int k) { return level0_matrices(bp.sys[k], Ad[k], As[k], fws).Ad; },
+                     [&](int k) { return level0_matrices(bp.sys[k], Ad[k], As[k], fws).As; });
+                L.recs = dev;
+            } else {
+                const FacLv<T, T>* dev = nullptr;
+                FacLv<T, T>* h = tab.take<FacLv<T, T>>(m, &dev);
+                if (!h) return BDS_EWORKSPACE;
+                fill(h, [&](int k) { return (const T*)at<T>(fws, bp.sys[k].lv[l - 1].Adn); },
+                     [&](int k) { return (const T*)at<T>(fws, bp.sys[k].lv[l - 1].Asn); });
+                L.recs = dev;
             }
-        };
-        if (l == 0) {
-            const FacLv<T, double>* dev = nullptr;
-            FacLv<T, double>* h = tab.take<FacLv<T, double>>(m, &dev);
-            if (!h) return BDS_EWORKSPACE;
-            fill(h, [&](int k) { return level0_matrices(bp.sys[k], Ad[k], As[k], fws).Ad; },
-                 [&](int k) { return level0_matrices(bp.sys[k], Ad[k], As[k], fws).As; });
-            L.recs = dev;
-        } else {
-            const FacLv<T, T>* dev = nullptr;
-            FacLv<T, T>* h = tab.take<FacLv<T, T>>(m, &dev);
-            if (!h) return BDS_EWORKSPACE;
-            fill(h, [&](int k) { return (const T*)at<T>(fws, bp.sys[k].lv[l - 1].Adn); },
-                 [&](int k) { return (const T*)at<T>(fws, bp.sys[k].lv[l - 1].Asn); });
-            L.recs = dev;
+            auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
+            if (!fill_prefix(tab, m, &L.sd, [&](size_t i) { return units_fac_diag(M_of(i)); }, L.td) ||
+                !fill_prefix(tab, m, &L.sc, [&](size_t i) { return units_fac_couple(M_of(i), np); }, L.tc) ||
+                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_fac_schur(M_of(i), np); }, L.ts))
+                return BDS_EWORKSPACE;
         }
-        auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
-        auto np_of = [&](size_t i) { return (int)bp.sys[members[i]].np; };
-        if (!fill_prefix(tab, m, &L.sd, [&](size_t i) { return units_fac_diag(M_of(i)); }, L.td) ||
-            !fill_prefix(tab, m, &L.sc, [&](size_t i) { return units_fac_couple(M_of(i), np_of(i), 1); }, L.tc) ||
-            !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_fac_schur(M_of(i), np_of(i), 1); }, L.ts))
-            return BDS_EWORKSPACE;
     }
     // coarse systems: those with no reduction level read FP64 inputs, the others level blocks of type T
     std::vector<CoarseFac<double>> c0;
@@ -255,14 +276,14 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
     BDS_TRY(tab.upload(st));
 
     BDS_TRY(launch_pack_tab(pack_dev, pack_start, (int)packs.size(), pack_tot, st));
-    for (int l = 0; l < bp.nlev; ++l) {
-        const LevelTab& L = lt[l];
-        if (l == 0) {
+    // levels in order; the groups of one level are independent of each other
+    for (const LevelTab& L : lt) {
+        if (L.level == 0) {
             BDS_TRY(launch_factor_level<C, double>(FacLv<T, double>{}, static_cast<const FacLv<T, double>*>(L.recs),
-                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np_max, st));
+                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np, st));
         } else {
             BDS_TRY(launch_factor_level<C, T>(FacLv<T, T>{}, static_cast<const FacLv<T, T>*>(L.recs), L.sd, L.sc,
-                                              L.ss, L.cnt, L.td, L.tc, L.ts, L.np_max, st));
+                                              L.ss, L.cnt, L.td, L.tc, L.ts, L.np, st));
         }
     }
     int np0 = 16, np1 = 16;
@@ -280,39 +301,43 @@ int solve_core_batched(const BatchPlan& bp, const std::vector<int>& act, const v
 {
     Table tab(sws, bp.stab, bp.stab_bytes);
     struct LevelTab {
+        int level, np;
         const SolLv<T>* recs;
         const int64_t *si, *ss, *sb;
         int64_t ti, ts, tb;
         int cnt;
     };
-    std::vector<LevelTab> lt((size_t)bp.nlev);
+    std::vector<LevelTab> lt;
     for (int l = 0; l < bp.nlev; ++l) {
-        std::vector<int> members;
-        for (int k : act)
-            if ((int)bp.sys[k].lv.size() > l) members.push_back(k);
-        LevelTab& L = lt[l];
-        L.cnt = (int)members.size();
-        const size_t m = members.size();
-        SolLv<T>* h = tab.take<SolLv<T>>(m, &L.recs);
-        if (!h) return BDS_EWORKSPACE;
-        for (size_t i = 0; i < m; ++i) {
-            const int k = members[i];
-            const SysPlan& p = bp.sys[k];
-            const LevelPlan& V = p.lv[l];
-            const double* B = l == 0 ? B0[k] : at<double>(sws, p.lv[l - 1].Bn);
-            double* X = l == 0 ? X0[k] : at<double>(sws, p.lv[l - 1].Xn);
-            h[i] = SolLv<T>{at<T>(fws, V.Li), at<T>(fws, V.Wl), at<T>(fws, V.Pr), B, at<double>(sws, V.Y),
-                            at<double>(sws, V.Bn), at<double>(sws, V.Xn), X, (int)V.M, (int)p.np, (int)p.d, 0};
+        for (const int np : bp.nps) {
+            std::vector<int> members;
+            for (int k : act)
+                if ((int)bp.sys[k].lv.size() > l && (int)bp.sys[k].np == np) members.push_back(k);
+            if (members.empty()) continue;
+            lt.push_back(LevelTab{});
+            LevelTab& L = lt.back();
+            L.level = l;
+            L.np = np;
+            L.cnt = (int)members.size();
+            const size_t m = members.size();
+            SolLv<T>* h = tab.take<SolLv<T>>(m, &L.recs);
+            if (!h) return BDS_EWORKSPACE;
+            for (size_t i = 0; i < m; ++i) {
+                const int k = members[i];
+                const SysPlan& p = bp.sys[k];
+                const LevelPlan& V = p.lv[l];
+                const double* B = l == 0 ? B0[k] : at<double>(sws, p.lv[l - 1].Bn);
+                double* X = l == 0 ? X0[k] : at<double>(sws, p.lv[l - 1].Xn);
+                h[i] = SolLv<T>{at<T>(fws, V.Li), at<T>(fws, V.Wt), at<T>(fws, V.Pr), B, at<double>(sws, V.Y),
+                                at<double>(sws, V.Bn), at<double>(sws, V.Xn), X, (int)V.M, (int)p.np, (int)p.d, 0};
+            }
+            auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
+            auto d_of = [&](size_t i) { return (int)bp.sys[members[i]].d; };
+            if (!fill_prefix(tab, m, &L.si, [&](size_t i) { return units_sol_fwd_int(M_of(i), np, d_of(i)); }, L.ti) ||
+                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_sol_fwd_sep(M_of(i), np, d_of(i)); }, L.ts) ||
+                !fill_prefix(tab, m, &L.sb, [&](size_t i) { return units_sol_bwd(M_of(i), d_of(i)); }, L.tb))
+                return BDS_EWORKSPACE;
         }
-        auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
-        auto np_of = [&](size_t i) { return (int)bp.sys[members[i]].np; };
-        auto d_of = [&](size_t i) { return (int)bp.sys[members[i]].d; };
-        if (!fill_prefix(tab, m, &L.si, [&](size_t i) { return units_sol_fwd_int(M_of(i), np_of(i), d_of(i), 1); },
-                         L.ti) ||
-            !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_sol_fwd_sep(M_of(i), np_of(i), d_of(i), 1); },
-                         L.ts) ||
-            !fill_prefix(tab, m, &L.sb, [&](size_t i) { return units_sol_bwd(M_of(i), d_of(i)); }, L.tb))
-            return BDS_EWORKSPACE;
     }
     const size_t m = act.size();
     const CoarseSol* cdev = nullptr;
@@ -331,15 +356,11 @@ int solve_core_batched(const BatchPlan& bp, const std::vector<int>& act, const v
     if (!fill_prefix(tab, m, &cstart, [&](size_t i) { return (bp.sys[act[i]].d + 15) / 16; }, ctot))
         return BDS_EWORKSPACE;
     BDS_TRY(tab.upload(st));
-    for (int l = 0; l < bp.nlev; ++l) {
-        const LevelTab& L = lt[l];
-        BDS_TRY(launch_solve_fwd<T>(SolLv<T>{}, L.recs, L.si, L.ss, L.cnt, L.ti, L.ts, 16, st));
-    }
+    for (const LevelTab& L : lt)
+        BDS_TRY(launch_solve_fwd<T>(SolLv<T>{}, L.recs, L.si, L.ss, L.cnt, L.ti, L.ts, L.np, st));
     BDS_TRY(launch_coarse_solve(CoarseSol{}, cdev, cstart, (int)m, ctot, st));
-    for (int l = bp.nlev - 1; l >= 0; --l) {
-        const LevelTab& L = lt[l];
-        BDS_TRY(launch_solve_bwd<T>(SolLv<T>{}, L.recs, L.sb, L.cnt, L.tb, 16, st));
-    }
+    for (auto it = lt.rbegin(); it != lt.rend(); ++it)
+        BDS_TRY(launch_solve_bwd<T>(SolLv<T>{}, it->recs, it->sb, it->cnt, it->tb, it->np, st));
     return BDS_OK;
 }
 
@@ -386,29 +407,49 @@ int refined_solve_batched(const BatchPlan& bp, const void* fws, const std::vecto
     for (int it = 1; it <= p0.max_refine && !act.empty(); ++it) {
         Table tab(sws, bp.rtab, bp.rtab_bytes);
         const size_t m = act.size();
-        const ResidArgs* rdev = nullptr;
         const AxpyArgs* xdev = nullptr;
-        ResidArgs* rh = tab.take<ResidArgs>(m, &rdev);
         AxpyArgs* xh = tab.take<AxpyArgs>(m, &xdev);
-        if (!rh || !xh) return BDS_EWORKSPACE;
+        if (!xh) return BDS_EWORKSPACE;
         for (size_t i = 0; i < m; ++i) {
             const int k = act[i];
             const SysPlan& p = bp.sys[k];
-            rh[i] = ResidArgs{a0[k].Ad, a0[k].As, B0[k], X0[k], Rp[k], (int)p.N, (int)p.np, (int)p.d, 0};
             xh[i] = AxpyArgs{X0[k], Cp[k], at<double>(sws, p.Nrm), nrm + 2 * k, (int)p.N, (int)p.np, (int)p.d, 0};
         }
-        const int64_t *rs = nullptr, *xs = nullptr;
-        int64_t rt = 0, xt = 0;
-        if (!fill_prefix(tab, m, &rs,
-                         [&](size_t i) {
-                             const SysPlan& p = bp.sys[act[i]];
-                             return units_resid((int)p.N, (int)p.np, (int)p.d, 1);
-                         },
-                         rt) ||
-            !fill_prefix(tab, m, &xs, [&](size_t i) { return bp.sys[act[i]].N; }, xt))
-            return BDS_EWORKSPACE;
+        const int64_t* xs = nullptr;
+        int64_t xt = 0;
+        if (!fill_prefix(tab, m, &xs, [&](size_t i) { return bp.sys[act[i]].N; }, xt)) return BDS_EWORKSPACE;
+        // residuals, one launch per block-size group
+        struct ResTab {
+            const ResidArgs* recs;
+            const int64_t* start;
+            int64_t tot;
+            int cnt, np;
+        };
+        std::vector<ResTab> rts;
+        for (const int np : bp.nps) {
+            std::vector<int> members;
+            for (int k : act)
+                if ((int)bp.sys[k].np == np) members.push_back(k);
+            if (members.empty()) continue;
+            ResTab r{nullptr, nullptr, 0, (int)members.size(), np};
+            ResidArgs* rh = tab.take<ResidArgs>(members.size(), &r.recs);
+            if (!rh) return BDS_EWORKSPACE;
+            for (size_t i = 0; i < members.size(); ++i) {
+                const int k = members[i];
+                const SysPlan& p = bp.sys[k];
+                rh[i] = ResidArgs{a0[k].Ad, a0[k].As, B0[k], X0[k], Rp[k], (int)p.N, (int)p.np, (int)p.d, 0};
+            }
+            if (!fill_prefix(tab, members.size(), &r.start,
+                             [&](size_t i) {
+                                 const SysPlan& p = bp.sys[members[i]];
+                                 return units_resid((int)p.N, np, (int)p.d);
+                             },
+                             r.tot))
+                return BDS_EWORKSPACE;
+            rts.push_back(r);
+        }
         BDS_TRY(tab.upload(st));
-        BDS_TRY(launch_residual(ResidArgs{}, rdev, rs, (int)m, rt, 16, st));
+        for (const ResTab& r : rts) BDS_TRY(launch_residual(ResidArgs{}, r.recs, r.start, r.cnt, r.tot, r.np, st));
         rc = solve_core_batched<T>(bp, act, fws, sws, std::vector<const double*>(Rp.begin(), Rp.end()), Cp, st);
         if (rc != BDS_OK) return rc;
         BDS_TRY(launch_axpy_norm(AxpyArgs{}, xdev, xs, (int)m, xt, st));

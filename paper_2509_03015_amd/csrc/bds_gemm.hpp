@@ -85,25 +85,47 @@ __device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[Chun
     }
 }
 
-// Triangular structure of term 0 that lets whole 16 x 16 output tiles skip
-// a chunk: A lower triangular (row m needs k <= m), or B^T lower triangular
-// (column n needs k <= n).
-enum { TRI_NONE = 0, TRI_A_ROWS = 1, TRI_B_COLS = 2 };
+// Work skipped under a triangle: none; SKIP_TRI_B, term 0's B^T is lower
+// triangular (column n of the output needs k <= n only); SKIP_SYM, the output
+// tile is a diagonal tile of a symmetric matrix of which only the lower
+// triangle is kept (16 x 16 tiles strictly above the diagonal are left out).
+enum { SKIP_NONE = 0, SKIP_TRI_B = 1, SKIP_SYM = 2 };
+
+// Accumulator tiles (ta, tb), bit ta * R + tb, of wave (wm, wn) that take part.
+template <int R> constexpr unsigned mask_cols_from(int tb0)
+{
+    unsigned m = 0;
+    for (int ta = 0; ta < R; ++ta)
+        for (int tb = tb0; tb < R; ++tb) m |= 1u << (ta * R + tb);
+    return m;
+}
+template <int R> constexpr unsigned mask_lower(int w)
+{
+    unsigned m = 0;
+    for (int ta = 0; ta < R; ++ta)
+        for (int tb = 0; tb < R; ++tb)
+            if ((w & 1) + 2 * tb <= (w >> 1) + 2 * ta) m |= 1u << (ta * R + tb);
+    return m;
+}
 
 // Accumulate the terms into acc.  Wave (wm, wn) of the 2 x 2 arrangement owns
 // the interleaved 16-row tiles wm, wm + 2, ... and 16-column tiles wn, wn + 2,
-// ... of the MT x MT tile, so that triangular skipping (tri, term 0 only)
-// spreads evenly over the waves.
-template <typename C, int MT, int NTERM, typename TA, typename TB>
+// ... of the MT x MT tile, so that work skipped under a triangle spreads over
+// the waves.  With a SKIP mode a chunk runs one of a few straight MFMA
+// sequences, chosen once per chunk (SKIP_TRI_B: the wave's first column tile
+// with work left) or once per tile (SKIP_SYM, when sym is set: the wave's
+// tiles on or below the diagonal); a branch per MFMA would break the
+// accumulator chains apart.
+template <typename C, int MT, int NTERM, int SKIP = SKIP_NONE, typename TA, typename TB>
 __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT / 32][MT / 32],
-                                                const Term<TA, TB> (&terms)[NTERM], int m0, int n0, int tri,
-                                                GemmSmem<typename Stor<C>::type, MT>& sm)
+                                                const Term<TA, TB> (&terms)[NTERM], int m0, int n0,
+                                                GemmSmem<typename Stor<C>::type, MT>& sm, bool sym = false)
 {
     using V = typename Stor<C>::type;
     constexpr int R = MT / 32;
     constexpr int E = ChunkEpt<MT>::value;
     constexpr int LD = TileLd<V>::value;
-    const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    const int w = wave_id(), wm = w >> 1, wn = w & 1;
     const int l = lane_id(), i = l & 15, g = l >> 4;
 
     static_assert(NTERM == 1 || NTERM == 2, "one or two terms");
@@ -143,48 +165,79 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
             chunk_load<V, MT>(va, m0, k1, ra);
             chunk_load<V, MT>(vb, n0, k1, rb);
         }
-        int tc, kcur;
-        locate(c, tc, kcur);
-        // tile (ta, tb) takes part in this chunk unless term 0's triangle rules it out
-        auto active = [&](int ta, int tb) {
-            if (tc != 0 || tri == TRI_NONE) return true;
-            if (tri == TRI_A_ROWS) return kcur < m0 + 16 * (wm + 2 * ta + 1);
-            return kcur < n0 + 16 * (wn + 2 * tb + 1);
-        };
         const V* As = sm.a[c & 1] + (16 * wm + i) * LD + 4 * g;
         const V* Bs = sm.b[c & 1] + (16 * wn + i) * LD + 4 * g;
-        if constexpr (std::is_same<C, bf16x>::value) {
-            V a[R][4], b[R][4];
+        // MFMAs of this chunk for the accumulator tiles in MASK
+        auto body = [&](auto mask_c) {
+            constexpr unsigned MASK = decltype(mask_c)::value;
+            auto on = [](int ta, int tb) { return ((MASK >> (ta * R + tb)) & 1u) != 0; };
+            auto col_on = [&](int tb) {
+                bool any = false;
+                for (int ta = 0; ta < R; ++ta) any = any || on(ta, tb);
+                return any;
+            };
+            if constexpr (std::is_same<C, bf16x>::value) {
+                V a[R][4], b[R][4];
 #pragma unroll
-            for (int ta = 0; ta < R; ++ta) ld4(As + 32 * ta * LD, a[ta]);
-#pragma unroll
-            for (int tb = 0; tb < R; ++tb) ld4(Bs + 32 * tb * LD, b[tb]);
-#pragma unroll
-            for (int ta = 0; ta < R; ++ta)
+                for (int ta = 0; ta < R; ++ta) ld4(As + 32 * ta * LD, a[ta]);
 #pragma unroll
                 for (int tb = 0; tb < R; ++tb)
-                    if (active(ta, tb)) tile_mac<C>(acc[ta][tb], a[ta], b[tb]);
-        } else {
-            // two k-steps at a time keeps the operand registers at 4 R
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                V a[R][2], b[R][2];
+                    if (col_on(tb)) ld4(Bs + 32 * tb * LD, b[tb]);
 #pragma unroll
                 for (int ta = 0; ta < R; ++ta)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) a[ta][q] = As[32 * ta * LD + 2 * h + q];
+                    for (int tb = 0; tb < R; ++tb)
+                        if (on(ta, tb)) tile_mac<C>(acc[ta][tb], a[ta], b[tb]);
+            } else {
+                // two k-steps at a time keeps the operand registers at 4 R
 #pragma unroll
-                for (int tb = 0; tb < R; ++tb)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) b[tb][q] = Bs[32 * tb * LD + 2 * h + q];
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
+                for (int h = 0; h < 2; ++h) {
+                    V a[R][2], b[R][2];
 #pragma unroll
                     for (int ta = 0; ta < R; ++ta)
 #pragma unroll
-                        for (int tb = 0; tb < R; ++tb)
-                            if (active(ta, tb)) acc[ta][tb] = mma(a[ta][q], b[tb][q], acc[ta][tb]);
+                        for (int q = 0; q < 2; ++q) a[ta][q] = As[32 * ta * LD + 2 * h + q];
+#pragma unroll
+                    for (int tb = 0; tb < R; ++tb)
+                        if (col_on(tb))
+#pragma unroll
+                            for (int q = 0; q < 2; ++q) b[tb][q] = Bs[32 * tb * LD + 2 * h + q];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+#pragma unroll
+                        for (int ta = 0; ta < R; ++ta)
+#pragma unroll
+                            for (int tb = 0; tb < R; ++tb)
+                                if (on(ta, tb)) acc[ta][tb] = mma(a[ta][q], b[tb][q], acc[ta][tb]);
+                }
             }
+        };
+        using std::integral_constant;
+        constexpr unsigned ALL = mask_cols_from<R>(0);
+        static_assert(R <= 4, "at most four tiles per wave and direction");
+        if constexpr (SKIP == SKIP_TRI_B) {
+            int tc, kc;
+            locate(c, tc, kc);
+            // column tile wn + 2 tb needs the chunks cr = (k - n0) / 16 <= wn + 2 tb
+            const int cr = (kc - n0) >> 4;
+            const int tb0 = (tc == 0 && cr > wn) ? (cr - wn + 1) >> 1 : 0;
+            switch (tb0) {
+            case 0: body(integral_constant<unsigned, ALL>{}); break;
+            case 1: body(integral_constant<unsigned, mask_cols_from<R>(1)>{}); break;
+            case 2: body(integral_constant<unsigned, mask_cols_from<R>(2)>{}); break;
+            case 3: body(integral_constant<unsigned, mask_cols_from<R>(3)>{}); break;
+            default: break;  // no column tile of this wave is reached yet
+            }
+        } else if constexpr (SKIP == SKIP_SYM) {
+            switch (sym ? w : 4) {
+            case 0: body(integral_constant<unsigned, mask_lower<R>(0)>{}); break;
+            case 1: body(integral_constant<unsigned, mask_lower<R>(1)>{}); break;
+            case 2: body(integral_constant<unsigned, mask_lower<R>(2)>{}); break;
+            case 3: body(integral_constant<unsigned, mask_lower<R>(3)>{}); break;
+            default: body(integral_constant<unsigned, ALL>{}); break;
+            }
+        } else {
+            body(integral_constant<unsigned, ALL>{});
         }
         if (c + 1 < nch) {
             chunk_store<MT>(kc_a, sm.a[(c + 1) & 1], ra);
@@ -201,7 +254,7 @@ __device__ __forceinline__ void wg_tile_foreach(const typename AccT<C>::type (&a
                                                 int n0, F f)
 {
     constexpr int R = MT / 32;
-    const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+    const int w = wave_id(), wm = w >> 1, wn = w & 1;
     const int l = lane_id(), i = l & 15, g = l >> 4;
 #pragma unroll
     for (int ta = 0; ta < R; ++ta)

@@ -3,17 +3,20 @@
 // Per reduction level (the paper's Alg. 4 with segment length 1):
 //   k_fac_diag    Li[e] = chol(A_ii)^-1 for every interior i = 2e+1
 //                 (potrf followed by an explicit triangular inverse)
-//   k_fac_couple  Wl[e] = Li[e] A_{i,i-1},  Pr[e] = A_{i+1,i} Li[e]^T
-//                 (the trsm of the coupling blocks, Alg. 4, as MFMA products)
+//   k_fac_couple  Wt[e] = A_{i-1,i} Li[e]^T,  Pr[e] = A_{i+1,i} Li[e]^T
+//                 (the trsm of the coupling blocks, Alg. 4, as MFMA products;
+//                 the left coupling Li A_{i,i-1} is kept transposed, as Wt, so
+//                 that every Schur product below reads both operands along
+//                 contiguous rows)
 //   k_fac_schur   next level S (eq. (5), Alg. 3), one record per separator j:
-//                 S_jj      = A_{2j,2j} - Pr[j-1] Pr[j-1]^T - Wl[j]^T Wl[j]
-//                 S_{j+1,j} = -Pr[j] Wl[j]
+//                 S_jj      = A_{2j,2j} - Pr[j-1] Pr[j-1]^T - Wt[j] Wt[j]^T
+//                 S_{j+1,j} = -Pr[j] Wt[j]^T
 //   k_coarse_factor  sequential block Cholesky of the coarse system (FP64).
 // Per solve level (Alg. 5-7):
 //   k_sol_fwd_int  Y[e] = Li[e] B_i
-//   k_sol_fwd_sep  B'_j = B_2j - Pr[j-1] Y[j-1] - Wl[j]^T Y[j]  (Alg. 5)
+//   k_sol_fwd_sep  B'_j = B_2j - Pr[j-1] Y[j-1] - Wt[j] Y[j]  (Alg. 5)
 //   k_coarse_solve block forward/backward substitution of the coarse system
-//   k_sol_bwd      X_i = Li[e]^T (Y[e] - Wl[e] X_{i-1} - Pr[e]^T X_{i+1})
+//   k_sol_bwd      X_i = Li[e]^T (Y[e] - Wt[e]^T X_{i-1} - Pr[e]^T X_{i+1})
 //                  (Alg. 6 followed by the interior solve), separators copied
 //                  from the coarser level (the final Assemble of Alg. 7).
 // Each separator receives its two contributions in a fixed order, so results
@@ -64,29 +67,34 @@ template <typename S> struct Many {
 };
 
 int tile_r(int np) { return (np % 32 == 0) ? 2 : 1; }
+bool fac_tiles_wg(int np) { return np % 64 == 0; }
 
+static int64_t units_fac_couple_wg(int M, int np, int MT);
+static int64_t units_fac_schur_wg(int M, int np, int MT);
 int64_t units_fac_diag(int M) { return M / 2; }
-int64_t units_fac_couple(int M, int np, int R)
+int64_t units_fac_couple(int M, int np)
 {
-    const int tp = np / (16 * R);
+    if (fac_tiles_wg(np)) return units_fac_couple_wg(M, np, 64);
+    const int tp = np / (16 * tile_r(np));
     return (int64_t)(M / 2) * 2 * tp * tp;
 }
-int64_t units_fac_schur(int M, int np, int R)
+int64_t units_fac_schur(int M, int np)
 {
-    const int tp = np / (16 * R);
+    if (fac_tiles_wg(np)) return units_fac_schur_wg(M, np, 64);
+    const int tp = np / (16 * tile_r(np));
     return (int64_t)((M + 1) / 2) * (tp * (tp + 1) / 2 + tp * tp);
 }
 static inline int dchunks(int d) { return (d + 15) / 16; }
-int64_t units_sol_fwd_int(int M, int np, int d, int R)
+int64_t units_sol_fwd_int(int M, int np, int d)
 {
-    return (int64_t)(M / 2) * (np / (16 * R)) * dchunks(d);
+    return (int64_t)(M / 2) * (np / (16 * tile_r(np))) * dchunks(d);
 }
-int64_t units_sol_fwd_sep(int M, int np, int d, int R)
+int64_t units_sol_fwd_sep(int M, int np, int d)
 {
-    return (int64_t)((M + 1) / 2) * (np / (16 * R)) * dchunks(d);
+    return (int64_t)((M + 1) / 2) * (np / (16 * tile_r(np))) * dchunks(d);
 }
 int64_t units_sol_bwd(int M, int d) { return (int64_t)(M / 2) * dchunks(d); }
-int64_t units_resid(int N, int np, int d, int R) { return (int64_t)N * (np / (16 * R)) * dchunks(d); }
+int64_t units_resid(int N, int np, int d) { return (int64_t)N * (np / (16 * tile_r(np))) * dchunks(d); }
 
 // ---------------------------------------------------------------------------
 // factorisation
@@ -130,10 +138,10 @@ __global__ __launch_bounds__(256) void k_fac_couple(Tab tab)
     A acc[R][R];
     acc_zero<C, R, R>(acc);
     if (which == 0) {
-        // Wl = Li * A[i,i-1]; Li is lower triangular: k < m0 + 16R
-        wave_mma<C, R, R, true, false>(acc, Li + (int64_t)m0 * np, np, s.As + (i - 1) * nn + n0, np, 0, 0,
-                                       0, min(np, m0 + 16 * R));
-        T* out = s.Wl + e * nn;
+        // Wt = A[i,i-1]^T Li^T; Li^T upper: k < n0 + 16R
+        wave_mma<C, R, R, false, true>(acc, s.As + (i - 1) * nn + m0, np, Li + (int64_t)n0 * np, np, 0, 0, 0,
+                                       min(np, n0 + 16 * R));
+        T* out = s.Wt + e * nn;
         acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
     } else {
         if (i + 1 >= s.M) return;
@@ -173,8 +181,8 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
             wave_mma<C, R, R, true, true>(acc, P + (int64_t)m0 * np, np, P + (int64_t)n0 * np, np, 0, 0, 0, np);
         }
         if (2 * j + 1 < s.M) {
-            const T* W = s.Wl + j * nn;
-            wave_mma<C, R, R, false, false>(acc, W + m0, np, W + n0, np, 0, 0, 0, np);
+            const T* W = s.Wt + j * nn;
+            wave_mma<C, R, R, true, true>(acc, W + (int64_t)m0 * np, np, W + (int64_t)n0 * np, np, 0, 0, 0, np);
         }
         const In* a = s.Ad + 2 * j * nn;
         T* out = s.Adn + j * nn;
@@ -186,8 +194,8 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
         const int t = rem - tl;
         const int m0 = 16 * R * (t / tp), n0 = 16 * R * (t % tp);
         const T* P = s.Pr + j * nn;
-        const T* W = s.Wl + j * nn;
-        wave_mma<C, R, R, true, false>(acc, P + (int64_t)m0 * np, np, W + n0, np, 0, 0, 0, np);
+        const T* W = s.Wt + j * nn;
+        wave_mma<C, R, R, true, true>(acc, P + (int64_t)m0 * np, np, W + (int64_t)n0 * np, np, 0, 0, 0, np);
         T* out = s.Asn + j * nn;
         acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
     }
@@ -195,22 +203,23 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
 
 // Work-group versions of k_fac_couple / k_fac_schur for block sizes that are
 // a multiple of the macro tile MT (see bds_gemm.hpp).
-//   couple: unit = (interior e, product in {Wl, Pr}, macro tile)
-//   schur, DIAG: unit = (separator j, lower macro tile of S_jj)
-//   schur, !DIAG: unit = (separator j < Mn - 1, macro tile of S_{j+1,j})
-int64_t units_fac_couple_wg(int M, int np, int MT)
+//   couple: unit = (interior e, product in {Wt, Pr}, macro tile)
+//   schur:  unit = (separator j, tile): the lower macro tiles of S_jj, then the
+//           macro tiles of S_{j+1,j} (none for the last separator), so that the
+//           work-groups reading Wt[j] and Pr[j] run side by side
+static int64_t units_fac_couple_wg(int M, int np, int MT)
 {
     const int tp = np / MT;
     return (int64_t)(M / 2) * 2 * tp * tp;
 }
-int64_t units_fac_schur_wg(int M, int np, int MT, bool diag)
+static int64_t units_fac_schur_wg(int M, int np, int MT)
 {
-    const int tp = np / MT, Mn = (M + 1) / 2;
-    return diag ? (int64_t)Mn * (tp * (tp + 1) / 2) : (int64_t)(Mn - 1) * tp * tp;
+    const int tp = np / MT;
+    return (int64_t)((M + 1) / 2) * (tp * (tp + 1) / 2 + tp * tp);
 }
 
 template <typename C, typename In, int MT, typename Tab>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fac_couple_wg(Tab tab)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 64 ? 4 : 2))) void k_fac_couple_wg(Tab tab)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
@@ -228,26 +237,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int m0 = MT * (t / tp), n0 = MT * (t % tp);
     const int64_t i = 2 * e + 1;
     if (which == 1 && i + 1 >= s.M) return;
-    const T* Li = s.Li + e * nn;
     Acc acc[R][R];
     acc_zero<C, R, R>(acc);
-    T* out;
-    if (which == 0) {
-        // Wl = Li A[i,i-1]: Li is lower triangular, so k < m0 + MT
-        const Term<T, In> terms[1] = {{{Li, np, true}, {s.As + (i - 1) * nn, np, false}, 0, min(np, m0 + MT)}};
-        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, TRI_A_ROWS, sm);
-        out = s.Wl + e * nn;
-    } else {
-        // Pr = A[i+1,i] Li^T: k < n0 + MT
-        const Term<In, T> terms[1] = {{{s.As + i * nn, np, true}, {Li, np, true}, 0, min(np, n0 + MT)}};
-        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, TRI_B_COLS, sm);
-        out = s.Pr + e * nn;
-    }
+    // Wt = A[i,i-1]^T Li^T, Pr = A[i+1,i] Li^T; Li^T is upper triangular, so k < n0 + MT
+    const View<In> op = which == 0 ? View<In>{s.As + (i - 1) * nn, np, false} : View<In>{s.As + i * nn, np, true};
+    const Term<In, T> terms[1] = {{op, {s.Li + e * nn, np, true}, 0, min(np, n0 + MT)}};
+    wg_tile_product<C, MT, 1, SKIP_TRI_B>(acc, terms, m0, n0, sm);
+    T* out = (which == 0 ? s.Wt : s.Pr) + e * nn;
     wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
 }
 
-template <typename C, typename In, int MT, bool DIAG, typename Tab>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_fac_schur_wg(Tab tab)
+template <typename C, typename In, int MT, typename Tab>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 64 ? 4 : 2))) void k_fac_schur_wg(Tab tab)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
@@ -259,37 +260,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const auto& s = tab.get(u, loc);
     const int np = s.np, tp = np / MT;
     const int64_t nn = (int64_t)np * np;
-    Acc acc[R][R];
-    acc_zero<C, R, R>(acc);
-    if constexpr (DIAG) {
-        const int per = tp * (tp + 1) / 2;
-        const int64_t j = loc / per;
-        const int rem = (int)(loc % per);
+    const int tl = tp * (tp + 1) / 2;
+    const int64_t j = loc / (tl + tp * tp);
+    const int rem = (int)(loc % (tl + tp * tp));
+    const bool diag = rem < tl;
+    if (!diag && j >= (s.M + 1) / 2 - 1) return;
+    int m0, n0;
+    if (diag) {
         int tm = 0;
         while ((tm + 1) * (tm + 2) / 2 <= rem) ++tm;
-        const int tn = rem - tm * (tm + 1) / 2;
-        const int m0 = MT * tm, n0 = MT * tn;
-        // S_jj = A_jj - Pr(j-1) Pr(j-1)^T - Wl(j)^T Wl(j); absent terms have no chunks
-        const bool left = j >= 1, right = 2 * j + 1 < s.M;
-        const T* P = left ? s.Pr + (j - 1) * nn : s.Pr;
-        const T* W = right ? s.Wl + j * nn : s.Wl;
-        const Term<T, T> terms[2] = {{{P, np, true}, {P, np, true}, 0, left ? np : 0},
-                                     {{W, np, false}, {W, np, false}, 0, right ? np : 0}};
-        wg_tile_product<C, MT, 2>(acc, terms, m0, n0, TRI_NONE, sm);
+        m0 = MT * tm;
+        n0 = MT * (rem - tm * (tm + 1) / 2);
+    } else {
+        m0 = MT * ((rem - tl) / tp);
+        n0 = MT * ((rem - tl) % tp);
+    }
+    // off-diagonal: S_{j+1,j} = -Pr(j) Wt(j)^T
+    // diagonal: S_jj = A_jj - Pr(j-1) Pr(j-1)^T - Wt(j) Wt(j)^T; a term absent at
+    // either end of the chain gets no chunks (its pointers are not read)
+    View<T> a0{s.Pr + j * nn, np, true}, b0{s.Wt + j * nn, np, true};
+    const View<T> w{s.Wt + j * nn, np, true};
+    int k0end = np, k1end = 0;
+    if (diag) {
+        const bool left = j >= 1;
+        a0.p = b0.p = left ? s.Pr + (j - 1) * nn : s.Pr;
+        k0end = left ? np : 0;
+        k1end = 2 * j + 1 < s.M ? np : 0;
+    }
+    const Term<T, T> terms[2] = {{a0, b0, 0, k0end}, {w, w, 0, k1end}};
+    Acc acc[R][R];
+    acc_zero<C, R, R>(acc);
+    // only the lower triangle of S_jj is kept (every reader of a diagonal block
+    // reads its lower triangle): diagonal macro tiles skip their strictly upper
+    // 16 x 16 tiles and store no element above the diagonal
+    const bool sym = diag && m0 == n0;
+    wg_tile_product<C, MT, 2, SKIP_SYM>(acc, terms, m0, n0, sm, sym);
+    if (diag) {
         const In* a = s.Ad + 2 * j * nn;
         T* out = s.Adn + j * nn;
         wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) {
-            out[(int64_t)m * np + n] = (T)a[(int64_t)m * np + n] - v;
+            if (!sym || n <= m) out[(int64_t)m * np + n] = (T)a[(int64_t)m * np + n] - v;
         });
     } else {
-        const int64_t j = loc / (tp * tp);
-        const int t = (int)(loc % (tp * tp));
-        const int m0 = MT * (t / tp), n0 = MT * (t % tp);
-        // S_{j+1,j} = -Pr(j) Wl(j)
-        const T* P = s.Pr + j * nn;
-        const T* W = s.Wl + j * nn;
-        const Term<T, T> terms[1] = {{{P, np, true}, {W, np, false}, 0, np}};
-        wg_tile_product<C, MT, 1>(acc, terms, m0, n0, TRI_NONE, sm);
         T* out = s.Asn + j * nn;
         wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
     }
@@ -393,8 +405,8 @@ __global__ __launch_bounds__(256) void k_sol_fwd_sep(Tab tab)
         wave_mma<double, R, 1, true, false, true>(acc, s.Pr + (j - 1) * nn + (int64_t)m0 * np, np,
                                                   s.Y + (j - 1) * nd + c0, d, 0, 0, 0, np, d - c0);
     if (2 * j + 1 < s.M)
-        wave_mma<double, R, 1, false, false, true>(acc, s.Wl + j * nn + m0, np, s.Y + j * nd + c0, d, 0, 0, 0,
-                                                   np, d - c0);
+        wave_mma<double, R, 1, true, false, true>(acc, s.Wt + j * nn + (int64_t)m0 * np, np, s.Y + j * nd + c0, d,
+                                                  0, 0, 0, np, d - c0);
     const double* b = s.B + 2 * j * nd;
     double* out = s.Bn + j * nd;
     acc_foreach<double, R, 1>(acc, m0, c0, [&](int m, int n, double v) {
@@ -421,8 +433,8 @@ __global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
         const int m0 = 16 * R * t;
         A acc[R][1];
         acc_zero<double, R, 1>(acc);
-        wave_mma<double, R, 1, true, false, true>(acc, s.Wl + e * nn + (int64_t)m0 * np, np, s.Xn + e * nd + c0,
-                                                  d, 0, 0, 0, np, d - c0);
+        wave_mma<double, R, 1, false, false, true>(acc, s.Wt + e * nn + m0, np, s.Xn + e * nd + c0, d, 0, 0, 0,
+                                                   np, d - c0);
         if (i + 1 < s.M)
             wave_mma<double, R, 1, false, false, true>(acc, s.Pr + e * nn + m0, np, s.Xn + (e + 1) * nd + c0, d,
                                                        0, 0, 0, np, d - c0);
@@ -778,78 +790,54 @@ template <typename F> static hipError_t dispatch_nt(int np_max, F&& f)
     return f(NtTag<16>{});
 }
 
+// Run `launch(table)` on the single record (tab == nullptr) or on the K
+// records at tab with prefix sums start; the table's unit total is `total`.
+template <typename Rec, typename F>
+static hipError_t with_table(const Rec& one, const Rec* tab, const int64_t* start, int K, int64_t total, F&& launch)
+{
+    if (total <= 0) return hipSuccess;
+    if (!tab) return launch(One<Rec>{one, total});
+    return launch(Many<Rec>{tab, start, K, total});
+}
+
 template <typename C, typename In>
 hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                const FacLv<typename Stor<C>::type, In>* tab, const int64_t* sd,
                                const int64_t* sc, const int64_t* ss, int K, int64_t td, int64_t tc,
-                               int64_t ts, int np_max, hipStream_t st)
+                               int64_t ts, int np, hipStream_t st)
 {
-    const bool r2 = (np_max % 32 == 0);
-    if (!tab) {
-        One<FacLv<typename Stor<C>::type, In>> o{one, td};
-        if (td > 0) {
-            const hipError_t e = dispatch_nt(one.np, [&](auto nt) {
-                constexpr int NT = decltype(nt)::value;
-                BDS_TIMED("fac_diag", st,
-                          k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(o));
-                return hipGetLastError();
-            });
-            if (e != hipSuccess) return e;
-        }
-        const int M = one.M, np = one.np;
-        if (np % 64 == 0) {
-            // work-group tile products: 128-wide macro tiles where they fit, 64-wide
-            // lower tiles for the symmetric diagonal blocks
-            auto run = [&](auto mt_c, auto mtd_c) {
-                constexpr int MT = decltype(mt_c)::value, MTD = decltype(mtd_c)::value;
-                o.total = units_fac_couple_wg(M, np, MT);
-                if (o.total > 0)
-                    BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, MT><<<(unsigned)o.total, 256, 0, st>>>(o));
-                o.total = units_fac_schur_wg(M, np, MTD, true);
-                if (o.total > 0)
-                    BDS_TIMED("fac_schur", st,
-                              k_fac_schur_wg<C, In, MTD, true><<<(unsigned)o.total, 256, 0, st>>>(o));
-                o.total = units_fac_schur_wg(M, np, MT, false);
-                if (o.total > 0)
-                    BDS_TIMED("fac_schur_off", st,
-                              k_fac_schur_wg<C, In, MT, false><<<(unsigned)o.total, 256, 0, st>>>(o));
-            };
-            if (np % 128 == 0)
-                run(NtTag<128>{}, NtTag<64>{});
-            else
-                run(NtTag<64>{}, NtTag<64>{});
-        } else {
-            o.total = tc;
-            if (tc > 0) {
-                if (r2) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(o));
-                else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(o));
-            }
-            o.total = ts;
-            if (ts > 0) {
-                if (r2) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(o));
-                else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(o));
-            }
-        }
-    } else {
-        // batched: per-record np may differ; 16-row tiles are valid for every np
-        Many<FacLv<typename Stor<C>::type, In>> m{tab, sd, K, td};
-        if (td > 0) {
-            const hipError_t e = dispatch_nt(np_max, [&](auto nt) {
-                constexpr int NT = decltype(nt)::value;
-                BDS_TIMED("fac_diag", st,
-                          k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(m));
-                return hipGetLastError();
-            });
-            if (e != hipSuccess) return e;
-        }
-        m.start = sc;
-        m.total = tc;
-        if (tc > 0) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(m));
-        m.start = ss;
-        m.total = ts;
-        if (ts > 0) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(m));
+    hipError_t e = with_table(one, tab, sd, K, td, [&](auto t) {
+        return dispatch_nt(np, [&](auto nt) {
+            constexpr int NT = decltype(nt)::value;
+            BDS_TIMED("fac_diag", st, k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(t));
+            return hipGetLastError();
+        });
+    });
+    if (e != hipSuccess) return e;
+    if (fac_tiles_wg(np)) {
+        // work-group tile products on 64-wide macro tiles (four work-groups per CU)
+        e = with_table(one, tab, sc, K, tc, [&](auto t) {
+            BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64><<<(unsigned)tc, 256, 0, st>>>(t));
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+        return with_table(one, tab, ss, K, ts, [&](auto t) {
+            BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64><<<(unsigned)ts, 256, 0, st>>>(t));
+            return hipGetLastError();
+        });
     }
-    return hipGetLastError();
+    const bool r2 = tile_r(np) == 2;
+    e = with_table(one, tab, sc, K, tc, [&](auto t) {
+        if (r2) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(t));
+        else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(t));
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return with_table(one, tab, ss, K, ts, [&](auto t) {
+        if (r2) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(t));
+        else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(t));
+        return hipGetLastError();
+    });
 }
 
 template <typename In>
@@ -879,44 +867,33 @@ hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* t
 
 template <typename T>
 hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab, const int64_t* si, const int64_t* ss,
-                            int K, int64_t ti, int64_t ts, int np_max, hipStream_t st)
+                            int K, int64_t ti, int64_t ts, int np, hipStream_t st)
 {
-    const bool r2 = (np_max % 32 == 0);
-    if (!tab) {
-        One<SolLv<T>> o{one, ti};
-        if (ti > 0) {
-            if (r2) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2><<<grid_waves(ti), 256, 0, st>>>(o));
-            else BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(o));
-        }
-        o.total = ts;
-        if (ts > 0) {
-            if (r2) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 2><<<grid_waves(ts), 256, 0, st>>>(o));
-            else BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(o));
-        }
-    } else {
-        Many<SolLv<T>> m{tab, si, K, ti};
-        if (ti > 0) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(m));
-        m.start = ss;
-        m.total = ts;
-        if (ts > 0) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(m));
-    }
-    return hipGetLastError();
+    const bool r2 = tile_r(np) == 2;
+    hipError_t e = with_table(one, tab, si, K, ti, [&](auto t) {
+        if (r2) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2><<<grid_waves(ti), 256, 0, st>>>(t));
+        else BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(t));
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return with_table(one, tab, ss, K, ts, [&](auto t) {
+        if (r2) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 2><<<grid_waves(ts), 256, 0, st>>>(t));
+        else BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(t));
+        return hipGetLastError();
+    });
 }
 
 template <typename T>
 hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab, const int64_t* sb, int K, int64_t tb,
-                            int np_max, hipStream_t st)
+                            int np, hipStream_t st)
 {
-    if (tb <= 0) return hipSuccess;
-    if (!tab) {
-        One<SolLv<T>> o{one, tb};
-        if (np_max % 32 == 0) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2><<<(unsigned)tb, 256, 0, st>>>(o));
-        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(o));
-    } else {
-        Many<SolLv<T>> m{tab, sb, K, tb};
-        BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(m));
-    }
-    return hipGetLastError();
+    // a work-group's four waves share the np / (16 R) row tiles of one interior:
+    // 32-row tiles only where that still leaves a tile per wave
+    return with_table(one, tab, sb, K, tb, [&](auto t) {
+        if (tile_r(np) == 2 && np >= 128) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2><<<(unsigned)tb, 256, 0, st>>>(t));
+        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(t));
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_coarse_solve(const CoarseSol& one, const CoarseSol* tab, const int64_t* start, int K,
@@ -935,18 +912,13 @@ hipError_t launch_coarse_solve(const CoarseSol& one, const CoarseSol* tab, const
 }
 
 hipError_t launch_residual(const ResidArgs& one, const ResidArgs* tab, const int64_t* start, int K, int64_t tot,
-                           int np_max, hipStream_t st)
+                           int np, hipStream_t st)
 {
-    if (tot <= 0) return hipSuccess;
-    if (!tab) {
-        One<ResidArgs> o{one, tot};
-        if (np_max % 32 == 0) BDS_TIMED("residual", st, k_residual<2><<<grid_waves(tot), 256, 0, st>>>(o));
-        else BDS_TIMED("residual", st, k_residual<1><<<grid_waves(tot), 256, 0, st>>>(o));
-    } else {
-        Many<ResidArgs> m{tab, start, K, tot};
-        BDS_TIMED("residual", st, k_residual<1><<<grid_waves(tot), 256, 0, st>>>(m));
-    }
-    return hipGetLastError();
+    return with_table(one, tab, start, K, tot, [&](auto t) {
+        if (tile_r(np) == 2) BDS_TIMED("residual", st, k_residual<2><<<grid_waves(tot), 256, 0, st>>>(t));
+        else BDS_TIMED("residual", st, k_residual<1><<<grid_waves(tot), 256, 0, st>>>(t));
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_axpy_norm(const AxpyArgs& one, const AxpyArgs* tab, const int64_t* start, int K, int64_t tot,

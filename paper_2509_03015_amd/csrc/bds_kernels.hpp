@@ -19,7 +19,7 @@ template <typename T, typename In> struct FacLv {
     const In* Ad;   // M diagonal blocks of this level (np x np, lower triangle read)
     const In* As;   // M-1 sub-diagonal blocks
     T* Li;          // E interiors: inverse Cholesky factor
-    T* Wl;          // E interiors: Li * A[i,i-1]
+    T* Wt;          // E interiors: A[i-1,i] * Li^T  (= (Li A[i,i-1])^T)
     T* Pr;          // E interiors: A[i+1,i] * Li^T
     T* Adn;         // Mn next-level diagonal blocks
     T* Asn;         // Mn-1 next-level sub-diagonal blocks
@@ -41,7 +41,7 @@ template <typename In> struct CoarseFac {
 // One reduction level of one system (solve); vectors FP64, np x d blocks, ld d.
 template <typename T> struct SolLv {
     const T* Li;
-    const T* Wl;
+    const T* Wt;
     const T* Pr;
     const double* B;   // M blocks: right-hand side of this level
     double* Y;         // E blocks
@@ -95,17 +95,19 @@ struct PackRec {
 };
 
 // Work-unit counts per record (waves for wave kernels, work-groups otherwise).
-// R is the wave tile factor: a wave computes (16R) x (16R) output tiles.  The
-// single-system launchers use R = tile_r(np); the table-driven (batched)
-// launchers always use R = 1, which is valid for every np.
+// The tiling depends on the block size np only: wave kernels compute
+// (16R) x (16R) output tiles with R = tile_r(np); blocks that are a multiple
+// of 64 (fac_tiles_wg) use the work-group tile products for the couplings and
+// Schur updates.  A table passed to a launcher holds records of one np.
 int tile_r(int np);
+bool fac_tiles_wg(int np);
 int64_t units_fac_diag(int M);
-int64_t units_fac_couple(int M, int np, int R);
-int64_t units_fac_schur(int M, int np, int R);
-int64_t units_sol_fwd_int(int M, int np, int d, int R);
-int64_t units_sol_fwd_sep(int M, int np, int d, int R);
+int64_t units_fac_couple(int M, int np);
+int64_t units_fac_schur(int M, int np);
+int64_t units_sol_fwd_int(int M, int np, int d);
+int64_t units_sol_fwd_sep(int M, int np, int d);
 int64_t units_sol_bwd(int M, int d);
-int64_t units_resid(int N, int np, int d, int R);
+int64_t units_resid(int N, int np, int d);
 
 // Launchers.  tab_dev/start_dev == nullptr: single record passed by value.
 // Otherwise K records at tab_dev with exclusive prefix sums start_dev (K+1).
@@ -115,7 +117,7 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                const FacLv<typename Stor<C>::type, In>* tab_dev,
                                const int64_t* start_diag, const int64_t* start_couple,
                                const int64_t* start_schur, int K, int64_t tot_diag,
-                               int64_t tot_couple, int64_t tot_schur, int np_max, hipStream_t st);
+                               int64_t tot_couple, int64_t tot_schur, int np, hipStream_t st);
 
 template <typename In>
 hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab_dev, int K, int np_max,
@@ -124,17 +126,17 @@ hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* t
 template <typename T>
 hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab_dev, const int64_t* start_int,
                             const int64_t* start_sep, int K, int64_t tot_int, int64_t tot_sep,
-                            int np_max, hipStream_t st);
+                            int np, hipStream_t st);
 
 template <typename T>
 hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab_dev, const int64_t* start,
-                            int K, int64_t tot, int np_max, hipStream_t st);
+                            int K, int64_t tot, int np, hipStream_t st);
 
 hipError_t launch_coarse_solve(const CoarseSol& one, const CoarseSol* tab_dev, const int64_t* start,
                                int K, int64_t tot, hipStream_t st);
 
 hipError_t launch_residual(const ResidArgs& one, const ResidArgs* tab_dev, const int64_t* start, int K,
-                           int64_t tot, int np_max, hipStream_t st);
+                           int64_t tot, int np, hipStream_t st);
 
 hipError_t launch_axpy_norm(const AxpyArgs& one, const AxpyArgs* tab_dev, const int64_t* start, int K,
                             int64_t tot, hipStream_t st);

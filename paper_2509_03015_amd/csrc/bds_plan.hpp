@@ -43,7 +43,7 @@ struct LevelPlan {
     int64_t Mn = 0;  // blocks of the next level: (M + 1) / 2
     // factor workspace byte offsets; matrix precision, np x np blocks
     size_t Li = 0;   // E blocks: inverse of the Cholesky factor of each interior
-    size_t Wl = 0;   // E blocks: Li * A[i, i-1]   (left coupling, solved)
+    size_t Wt = 0;   // E blocks: A[i-1, i] * Li^T (left coupling, solved and stored transposed)
     size_t Pr = 0;   // E blocks: A[i+1, i] * Li^T (right coupling, solved, transposed)
     size_t Adn = 0;  // Mn blocks: next level diagonal blocks (Schur complement)
     size_t Asn = 0;  // Mn - 1 blocks: next level sub-diagonal blocks
