@@ -52,10 +52,12 @@ template <typename T, int NT> struct CholSmem {
 };
 
 // Compute waves per work-group for a tile bound NT; the work-group has one
-// more wave, the pivot wave, so it runs 64 (W + 1) threads.  Up to NT = 8 the
-// work-group is 4 waves, one per SIMD, so that several work-groups share a
-// CU (waves are dealt to the SIMDs round-robin).
-template <int NT> struct CholWaves { static constexpr int value = NT <= 8 ? 3 : 15; };
+// more wave, the pivot wave, so it runs 64 (W + 1) threads.  Blocks of one or
+// two tile columns (at most three tiles) get a single compute wave, so that
+// twice as many work-groups fit on a CU; up to NT = 8 the work-group is 4
+// waves, one per SIMD, so that several work-groups share a CU (waves are
+// dealt to the SIMDs round-robin).
+template <int NT> struct CholWaves { static constexpr int value = NT <= 2 ? 1 : (NT <= 8 ? 3 : 15); };
 template <int NT> constexpr int chol_threads() { return 64 * (CholWaves<NT>::value + 1); }
 
 // Value of lane R of each 16-lane row, broadcast to the whole row (DPP

@@ -21,6 +21,8 @@
 //                  from the coarser level (the final Assemble of Alg. 7).
 // Each separator receives its two contributions in a fixed order, so results
 // are deterministic (no atomics in the arithmetic).
+#include <algorithm>
+
 #include "bds_chol.hpp"
 #include "bds_device.hpp"
 #include "bds_gemm.hpp"
@@ -414,22 +416,25 @@ __global__ __launch_bounds__(256) void k_sol_fwd_sep(Tab tab)
     });
 }
 
+// One work-group of min(4, np / 16R) waves per (interior, 16 columns); the
+// launch provides np * 16 doubles of dynamic LDS for the corrected right-hand side.
 template <typename T, int R, typename Tab>
 __global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
 {
     using A = typename AccT<double>::type;
-    __shared__ double tsm[kMaxNP * 16];
+    extern __shared__ double tsm[];
     const int64_t u = blockIdx.x;
     if (u >= tab.total) return;
     int64_t loc;
     const auto& s = tab.get(u, loc);
     const int np = s.np, d = s.d, tp = np / (16 * R), dc = (d + 15) / 16, w = wave_id();
+    const int nw = blockDim.x >> 6;
     const int64_t nn = (int64_t)np * np, nd = (int64_t)np * d;
     const int64_t e = loc / dc;
     const int c0 = 16 * (int)(loc % dc);
     const int64_t i = 2 * e + 1;
     const int Mn = (s.M + 1) / 2;
-    for (int t = w; t < tp; t += 4) {
+    for (int t = w; t < tp; t += nw) {
         const int m0 = 16 * R * t;
         A acc[R][1];
         acc_zero<double, R, 1>(acc);
@@ -444,7 +449,7 @@ __global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
         });
     }
     __syncthreads();
-    for (int t = w; t < tp; t += 4) {
+    for (int t = w; t < tp; t += nw) {
         const int m0 = 16 * R * t;
         A acc[R][1];
         acc_zero<double, R, 1>(acc);
@@ -889,9 +894,12 @@ hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab, const int6
 {
     // a work-group's four waves share the np / (16 R) row tiles of one interior:
     // 32-row tiles only where that still leaves a tile per wave
+    const int R = (tile_r(np) == 2 && np >= 128) ? 2 : 1;
+    const unsigned threads = 64u * (unsigned)std::min(4, np / (16 * R));
+    const size_t lds = (size_t)np * 16 * sizeof(double);
     return with_table(one, tab, sb, K, tb, [&](auto t) {
-        if (tile_r(np) == 2 && np >= 128) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2><<<(unsigned)tb, 256, 0, st>>>(t));
-        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, 256, 0, st>>>(t));
+        if (R == 2) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2><<<(unsigned)tb, threads, lds, st>>>(t));
+        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, threads, lds, st>>>(t));
         return hipGetLastError();
     });
 }
