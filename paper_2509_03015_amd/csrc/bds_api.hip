@@ -107,7 +107,7 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
         BDS_TRY(launch_pack_blocks(As, at<double>(fws, p.As0), p.N - 1, (int)p.n, (int)p.np, false, st));
     }
     const Level0 a0 = level0_matrices(p, Ad, As, fws);
-    const int np = (int)p.np;
+    const int np = (int)p.np, prec = PrecOf<C>::value;
     for (size_t l = 0; l < p.lv.size(); ++l) {
         const LevelPlan& L = p.lv[l];
         const int M = (int)L.M;
@@ -115,13 +115,14 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
             FacLv<T, double> r{a0.Ad, a0.As, at<T>(fws, L.Li), at<T>(fws, L.Wt), at<T>(fws, L.Pr),
                                at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, 0, 0, info};
             BDS_TRY(launch_factor_level<C, double>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                                   units_fac_couple(M, np), units_fac_schur(M, np), np, st));
+                                                   units_fac_couple(M, np, prec), units_fac_schur(M, np, prec),
+                                                   np, st));
         } else {
             const LevelPlan& P = p.lv[l - 1];
             FacLv<T, T> r{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<T>(fws, L.Li), at<T>(fws, L.Wt),
                           at<T>(fws, L.Pr), at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, (int)l, 0, info};
             BDS_TRY(launch_factor_level<C, T>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                              units_fac_couple(M, np), units_fac_schur(M, np), np, st));
+                                              units_fac_couple(M, np, prec), units_fac_schur(M, np, prec), np, st));
         }
     }
     const int Lv = (int)p.lv.size();

@@ -238,9 +238,10 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
                 L.recs = dev;
             }
             auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
+            constexpr int prec = PrecOf<C>::value;
             if (!fill_prefix(tab, m, &L.sd, [&](size_t i) { return units_fac_diag(M_of(i)); }, L.td) ||
-                !fill_prefix(tab, m, &L.sc, [&](size_t i) { return units_fac_couple(M_of(i), np); }, L.tc) ||
-                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_fac_schur(M_of(i), np); }, L.ts))
+                !fill_prefix(tab, m, &L.sc, [&](size_t i) { return units_fac_couple(M_of(i), np, prec); }, L.tc) ||
+                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_fac_schur(M_of(i), np, prec); }, L.ts))
                 return BDS_EWORKSPACE;
         }
     }

@@ -42,6 +42,10 @@ template <typename T> struct AccT;
 template <> struct AccT<double> { using type = dx4; };
 template <> struct AccT<float> { using type = fx4; };
 template <> struct AccT<bf16x> { using type = fx4; };
+// The library's precision code (BDS_F64, BDS_F32, BDS_BF16) of a compute tag.
+template <typename C> struct PrecOf { static constexpr int value = 0; };
+template <> struct PrecOf<float> { static constexpr int value = 1; };
+template <> struct PrecOf<bf16x> { static constexpr int value = 2; };
 
 // FP32 -> bfloat16 bits, round to nearest even; NaN stays NaN.
 __device__ __forceinline__ short bf16_bits(float x)

@@ -70,19 +70,30 @@ template <typename S> struct Many {
 
 int tile_r(int np) { return (np % 32 == 0) ? 2 : 1; }
 bool fac_tiles_wg(int np) { return np % 64 == 0; }
+// Macro tile of the work-group tile products by compute precision.  FP64: 64
+// (four work-groups per CU keep enough HBM reads in flight).  The FP32 and BF16
+// MFMAs take 1/2 and 1/8 the cycles of FP64 per k step, so a 64-wide tile spends
+// relatively more time per chunk on loads, LDS staging and the barrier; 128-wide
+// tiles halve that overhead per flop where np allows: for both products in BF16,
+// for the couplings in FP32 (measured: the FP32 Schur update is faster with 64).
+static_assert(PrecOf<double>::value == BDS_F64 && PrecOf<float>::value == BDS_F32 &&
+                  PrecOf<bf16x>::value == BDS_BF16,
+              "precision codes of the compute tags");
+int fac_mt_couple(int np, int prec) { return (prec != BDS_F64 && np % 128 == 0) ? 128 : 64; }
+int fac_mt_schur(int np, int prec) { return (prec == BDS_BF16 && np % 128 == 0) ? 128 : 64; }
 
 static int64_t units_fac_couple_wg(int M, int np, int MT);
 static int64_t units_fac_schur_wg(int M, int np, int MT);
 int64_t units_fac_diag(int M) { return M / 2; }
-int64_t units_fac_couple(int M, int np)
+int64_t units_fac_couple(int M, int np, int prec)
 {
-    if (fac_tiles_wg(np)) return units_fac_couple_wg(M, np, 64);
+    if (fac_tiles_wg(np)) return units_fac_couple_wg(M, np, fac_mt_couple(np, prec));
     const int tp = np / (16 * tile_r(np));
     return (int64_t)(M / 2) * 2 * tp * tp;
 }
-int64_t units_fac_schur(int M, int np)
+int64_t units_fac_schur(int M, int np, int prec)
 {
-    if (fac_tiles_wg(np)) return units_fac_schur_wg(M, np, 64);
+    if (fac_tiles_wg(np)) return units_fac_schur_wg(M, np, fac_mt_schur(np, prec));
     const int tp = np / (16 * tile_r(np));
     return (int64_t)((M + 1) / 2) * (tp * (tp + 1) / 2 + tp * tp);
 }
@@ -820,14 +831,21 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
     });
     if (e != hipSuccess) return e;
     if (fac_tiles_wg(np)) {
-        // work-group tile products on 64-wide macro tiles (four work-groups per CU)
+        // work-group tile products (macro tile by precision, see fac_mt_couple)
+        constexpr int prec = PrecOf<C>::value;
         e = with_table(one, tab, sc, K, tc, [&](auto t) {
-            BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64><<<(unsigned)tc, 256, 0, st>>>(t));
+            if (fac_mt_couple(np, prec) == 128)
+                BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 128><<<(unsigned)tc, 256, 0, st>>>(t));
+            else
+                BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64><<<(unsigned)tc, 256, 0, st>>>(t));
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
         return with_table(one, tab, ss, K, ts, [&](auto t) {
-            BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64><<<(unsigned)ts, 256, 0, st>>>(t));
+            if (fac_mt_schur(np, prec) == 128)
+                BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 128><<<(unsigned)ts, 256, 0, st>>>(t));
+            else
+                BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64><<<(unsigned)ts, 256, 0, st>>>(t));
             return hipGetLastError();
         });
     }

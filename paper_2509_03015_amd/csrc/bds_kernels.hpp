@@ -98,12 +98,16 @@ struct PackRec {
 // The tiling depends on the block size np only: wave kernels compute
 // (16R) x (16R) output tiles with R = tile_r(np); blocks that are a multiple
 // of 64 (fac_tiles_wg) use the work-group tile products for the couplings and
-// Schur updates.  A table passed to a launcher holds records of one np.
+// Schur updates, whose macro tile also depends on the compute precision prec
+// (BDS_F64, BDS_F32, BDS_BF16).  A table passed to a launcher holds records of
+// one np.
 int tile_r(int np);
 bool fac_tiles_wg(int np);
 int64_t units_fac_diag(int M);
-int64_t units_fac_couple(int M, int np);
-int64_t units_fac_schur(int M, int np);
+int fac_mt_couple(int np, int prec);
+int fac_mt_schur(int np, int prec);
+int64_t units_fac_couple(int M, int np, int prec);
+int64_t units_fac_schur(int M, int np, int prec);
 int64_t units_sol_fwd_int(int M, int np, int d);
 int64_t units_sol_fwd_sep(int M, int np, int d);
 int64_t units_sol_bwd(int M, int d);
