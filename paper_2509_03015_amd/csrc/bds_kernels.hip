@@ -559,7 +559,9 @@ template <int R, typename Tab>
 __global__ __launch_bounds__(256) void k_residual(Tab tab)
 {
     using A = typename AccT<double>::type;
-    const int64_t u = (int64_t)blockIdx.x * 4 + wave_id();
+    // consecutive block rows on one XCD: rows i and i + 1 both read A_{i+1,i},
+    // and the second read then comes from that XCD's L2 instead of HBM
+    const int64_t u = xcd_local_index(blockIdx.x, gridDim.x) * 4 + wave_id();
     if (u >= tab.total) return;
     int64_t loc;
     const auto& s = tab.get(u, loc);

@@ -73,7 +73,9 @@ def test_f32_refined_kalman_n32(S, kappa):
     assert relerr(X, oracle.solve_ld(Ad, As, B)) <= 1e-10
 
 
-@pytest.mark.parametrize("N,n,d", [(1, 16, 1), (2, 17, 2), (37, 8, 3), (64, 40, 17), (129, 64, 1)])
+# n = 128 and 256 take the 128-wide coupling tiles of the FP32 path, n = 192 the 64-wide ones
+@pytest.mark.parametrize("N,n,d", [(1, 16, 1), (2, 17, 2), (37, 8, 3), (64, 40, 17), (129, 64, 1), (70, 128, 3),
+                                   (33, 192, 2), (20, 256, 1)])
 def test_f32_refined_dd_sweep(S, N, n, d):
     _say("mixed dd", N, n, d)
     Ad, As, _, B = inputs.gen_dd(N, n, d, seed=N + n)
@@ -122,7 +124,9 @@ def test_f32_full_size_kalman_kappa_1e4_properties(S):
     assert relerr(X, Xt) <= 1e-10
 
 
-@pytest.mark.parametrize("N,n,d", [(1, 16, 1), (37, 8, 3), (64, 40, 17), (129, 64, 1), (300, 128, 2)])
+# n = 128 and 256 take the 128-wide tiles of the BF16 path, n = 192 the 64-wide ones
+@pytest.mark.parametrize("N,n,d", [(1, 16, 1), (37, 8, 3), (64, 40, 17), (129, 64, 1), (300, 128, 2), (33, 192, 2),
+                                   (20, 256, 4)])
 def test_bf16_refined_dd_sweep(S, N, n, d):
     """BF16 MFMA operands with FP32 accumulation; FP64 refinement recovers FP64 accuracy at kappa ~ 4."""
     _say("bf16 dd", N, n, d)
