@@ -82,11 +82,30 @@ typedef struct bds_desc {
     int32_t nstar;      /* recursion stops once a level has <= nstar blocks
                            (the paper's crossover N_star); 0 = library choice */
     int32_t max_refine; /* refinement iteration cap for prec != BDS_F64; 0 = default (30) */
-    int32_t reserved;   /* must be 0 */
+    int32_t tiles;      /* tile shapes, BDS_TILES(couple, schur, solve); 0 = library rule */
     double refine_tol;  /* stop when the estimated remaining error is <= refine_tol * ||X||_F:
                            ||dX||_F itself, or rho * ||dX||_F once the contraction rho of
                            successive corrections is known; 0 = default (1e-14) */
 } bds_desc;
+
+/*
+ * Tile shapes (bds_desc.tiles).  Each field selects how one step of a
+ * reduction level is cut into work for the GPU; BDS_TILE_RULE leaves it to
+ * the library's rule (a function of the padded block size np and the
+ * precision), which is also what bds_tune starts from.
+ *   couple: the coupling products of Alg. 4 (trsm as products with the
+ *           stored inverse factor);
+ *   schur:  the Schur updates of Alg. 3;
+ *   solve:  the forward and backward sweeps of Alg. 5-7 (wave tiles only).
+ * BDS_TILE_W16 / W32: one wavefront per 16 x 16 / 32 x 32 output tile, operands
+ * read directly (W32 needs np % 32 == 0).  BDS_TILE_G64 / G128: a work-group
+ * of four wavefronts per 64 x 64 / 128 x 128 output tile, operands staged
+ * through LDS (need np % 64 == 0 / np % 128 == 0).  np = n rounded up to a
+ * multiple of 16.  A choice that does not fit np is rejected with BDS_EINVAL.
+ * Every choice computes the same result up to rounding.
+ */
+enum { BDS_TILE_RULE = 0, BDS_TILE_W16 = 1, BDS_TILE_W32 = 2, BDS_TILE_G64 = 3, BDS_TILE_G128 = 4 };
+#define BDS_TILES(couple, schur, solve) ((int32_t)((couple) | ((schur) << 4) | ((solve) << 8)))
 
 /* Device-side outcome record, written by the kernels (8 x int32). */
 typedef struct bds_info {
@@ -176,6 +195,39 @@ int bds_solve_batched(int64_t K, const bds_desc* descs, const void* factor_ws,
                       size_t factor_bytes, const double* const* Ad, const double* const* As,
                       const double* const* B, double* const* X, void* solve_ws,
                       size_t solve_bytes, bds_info* info, void* stream);
+
+/*
+ * Autotuner.  Times factor + solve of the caller's system for a sequence of
+ * configurations and writes the fastest descriptor to *best (nstar and tiles
+ * chosen; every other field copied from *desc).  Coordinate search from the
+ * library's choices: nstar over {1, 2, 4, ..., 64} (up to N), then each tile
+ * field over the shapes that fit np; each candidate is run once untimed and
+ * timed over `reps` runs (reps <= 0: 3) with HIP events on `stream`.  The
+ * search excludes workspace sizing and is meant to run once per problem
+ * shape, before the timed work (the paper's Init phase).
+ * Arguments as for bds_factor + bds_solve; the workspaces must have the sizes
+ * given by bds_tune_workspace_size (the largest over the candidates).  On
+ * return factor_ws holds the factor of *best and X its solution.  The stream
+ * is synchronised.  Returns BDS_OK or the first error of a candidate run;
+ * a candidate that reports a numerical failure in info ends the search with
+ * that status left in info.
+ */
+int bds_tune_workspace_size(const bds_desc* desc, size_t* factor_bytes, size_t* solve_bytes);
+int bds_tune(const bds_desc* desc, const double* Ad, const double* As, const double* B, double* X,
+             void* factor_ws, size_t factor_bytes, void* solve_ws, size_t solve_bytes, bds_info* info,
+             int reps, void* stream, bds_desc* best);
+
+/*
+ * Batched autotuner: the tile fields are chosen per padded block size np (all
+ * systems of one np share them), by coordinate search over each group's
+ * fields in turn, timing factor + solve of the whole batch.  nstar is kept.
+ * Workspaces as given by bds_batched_workspace_size for descs (tile choices
+ * do not change them).  best: host array of K descriptors.
+ */
+int bds_tune_batched(int64_t K, const bds_desc* descs, const double* const* Ad, const double* const* As,
+                     const double* const* B, double* const* X, void* factor_ws, size_t factor_bytes,
+                     void* solve_ws, size_t solve_bytes, bds_info* info, int reps, void* stream,
+                     bds_desc* best);
 
 /*
  * Kernel timing, for diagnostics and benchmarking; it does not change any

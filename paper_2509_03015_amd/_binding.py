@@ -19,13 +19,28 @@ BDS_F64, BDS_F32, BDS_BF16 = 0, 1, 2
 
 # Every function declared in include/bds.h.
 EXPORTS = ("bds_workspace_size", "bds_factor", "bds_solve", "bds_backward", "bds_batched_workspace_size",
-           "bds_factor_batched", "bds_solve_batched", "bds_trace_enable", "bds_trace_read", "bds_version")
+           "bds_factor_batched", "bds_solve_batched", "bds_tune_workspace_size", "bds_tune", "bds_tune_batched",
+           "bds_trace_enable", "bds_trace_read", "bds_version")
+
+# Tile shape codes of bds_desc.tiles (BDS_TILE_*) and the field packing of BDS_TILES.
+BDS_TILE_RULE, BDS_TILE_W16, BDS_TILE_W32, BDS_TILE_G64, BDS_TILE_G128 = range(5)
+TILE_NAMES = {0: "rule", 1: "w16", 2: "w32", 3: "g64", 4: "g128"}
+
+
+def tiles(couple: int = 0, schur: int = 0, solve: int = 0) -> int:
+    """BDS_TILES(couple, schur, solve)."""
+    return int(couple) | (int(schur) << 4) | (int(solve) << 8)
+
+
+def tiles_fields(t: int) -> dict:
+    """{"couple": name, "schur": name, "solve": name} of a bds_desc.tiles value."""
+    return {k: TILE_NAMES.get((int(t) >> (4 * i)) & 15, "?") for i, k in enumerate(("couple", "schur", "solve"))}
 
 
 class BdsDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("n", ctypes.c_int64), ("d", ctypes.c_int64),
                 ("prec", ctypes.c_int32), ("nstar", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+                ("tiles", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
 
 
 class BdsInfo(ctypes.Structure):
@@ -54,6 +69,9 @@ def load():
     lib.bds_factor_batched.argtypes = [I64, P, P, P, P, S, P, P]
     lib.bds_solve_batched.argtypes = [I64, P, P, S, P, P, P, P, P, S, P, P]
     lib.bds_batched_workspace_size.argtypes = [I64, P, PS, PS]
+    lib.bds_tune_workspace_size.argtypes = [D, PS, PS]
+    lib.bds_tune.argtypes = [D, P, P, P, P, P, S, P, S, P, ctypes.c_int, P, D]
+    lib.bds_tune_batched.argtypes = [I64, P, P, P, P, P, P, S, P, S, P, ctypes.c_int, P, P]
     lib.bds_trace_enable.argtypes = [I64]
     lib.bds_trace_read.argtypes = [I64, P, P, P, P, P]
     for f in EXPORTS[:-1]:
@@ -91,4 +109,11 @@ def workspace_size(desc: BdsDesc):
     f = ctypes.c_size_t(0)
     s = ctypes.c_size_t(0)
     rc = load().bds_workspace_size(ctypes.byref(desc), ctypes.byref(f), ctypes.byref(s))
+    return rc, f.value, s.value
+
+
+def tune_workspace_size(desc: BdsDesc):
+    f = ctypes.c_size_t(0)
+    s = ctypes.c_size_t(0)
+    rc = load().bds_tune_workspace_size(ctypes.byref(desc), ctypes.byref(f), ctypes.byref(s))
     return rc, f.value, s.value

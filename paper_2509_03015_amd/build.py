@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libbds.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("bds_kernels.hip", "bds_api.hip", "bds_batched.hip", "bds_trace.hip", "bds_graph.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("bds_kernels.hip", "bds_api.hip", "bds_batched.hip", "bds_trace.hip", "bds_graph.hip", "bds_tune.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

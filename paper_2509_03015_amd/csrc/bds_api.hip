@@ -23,7 +23,9 @@ int check_desc(const bds_desc* d)
     if (d->n < 1 || d->n > kMaxN) return BDS_EINVAL;
     if (d->d < 1 || d->d > 65536) return BDS_EINVAL;
     if (d->prec != BDS_F64 && d->prec != BDS_F32 && d->prec != BDS_BF16) return BDS_EINVAL;
-    if (d->nstar < 0 || d->max_refine < 0 || !(d->refine_tol >= 0) || d->reserved != 0) return BDS_EINVAL;
+    if (d->nstar < 0 || d->max_refine < 0 || !(d->refine_tol >= 0)) return BDS_EINVAL;
+    Tiling t;
+    if (!resolve_tiling((int)round_up(d->n, 16), d->prec, d->tiles, t)) return BDS_EINVAL;
     return BDS_OK;
 }
 
@@ -40,6 +42,7 @@ SysPlan make_plan(const bds_desc& d, size_t base_f, size_t base_s)
     p.refine_tol = d.refine_tol > 0 ? d.refine_tol : kDefaultRefineTol;
     p.esize = matrix_elem_bytes(d.prec);
     p.packed = p.np != p.n;
+    resolve_tiling((int)p.np, p.prec, d.tiles, p.tl);  // checked by check_desc
     size_t f = base_f, s = base_s;
     auto take = [](size_t& off, size_t bytes) {
         const size_t o = off;
@@ -107,7 +110,7 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
         BDS_TRY(launch_pack_blocks(As, at<double>(fws, p.As0), p.N - 1, (int)p.n, (int)p.np, false, st));
     }
     const Level0 a0 = level0_matrices(p, Ad, As, fws);
-    const int np = (int)p.np, prec = PrecOf<C>::value;
+    const int np = (int)p.np;
     for (size_t l = 0; l < p.lv.size(); ++l) {
         const LevelPlan& L = p.lv[l];
         const int M = (int)L.M;
@@ -115,14 +118,15 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
             FacLv<T, double> r{a0.Ad, a0.As, at<T>(fws, L.Li), at<T>(fws, L.Wt), at<T>(fws, L.Pr),
                                at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, 0, 0, info};
             BDS_TRY(launch_factor_level<C, double>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                                   units_fac_couple(M, np, prec), units_fac_schur(M, np, prec),
-                                                   np, st));
+                                                   units_fac_couple(M, np, p.tl.couple),
+                                                   units_fac_schur(M, np, p.tl.schur), np, p.tl, st));
         } else {
             const LevelPlan& P = p.lv[l - 1];
             FacLv<T, T> r{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<T>(fws, L.Li), at<T>(fws, L.Wt),
                           at<T>(fws, L.Pr), at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, (int)l, 0, info};
             BDS_TRY(launch_factor_level<C, T>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                              units_fac_couple(M, np, prec), units_fac_schur(M, np, prec), np, st));
+                                              units_fac_couple(M, np, p.tl.couple),
+                                              units_fac_schur(M, np, p.tl.schur), np, p.tl, st));
         }
     }
     const int Lv = (int)p.lv.size();
@@ -152,15 +156,15 @@ int solve_core(const SysPlan& p, const void* fws, void* sws, const double* B0, d
         double* X = l == 0 ? X0 : at<double>(sws, p.lv[l - 1].Xn);
         recs[l] = SolLv<T>{at<T>(fws, L.Li), at<T>(fws, L.Wt), at<T>(fws, L.Pr), B, at<double>(sws, L.Y),
                            at<double>(sws, L.Bn), at<double>(sws, L.Xn), X, (int)L.M, np, d, 0};
-        BDS_TRY(launch_solve_fwd<T>(recs[l], nullptr, nullptr, nullptr, 1, units_sol_fwd_int((int)L.M, np, d),
-                                    units_sol_fwd_sep((int)L.M, np, d), np, st));
+        BDS_TRY(launch_solve_fwd<T>(recs[l], nullptr, nullptr, nullptr, 1, units_sol_fwd_int((int)L.M, np, d, p.tl.sol),
+                                    units_sol_fwd_sep((int)L.M, np, d, p.tl.sol), np, p.tl, st));
     }
     CoarseSol c{at<double>(fws, p.Lc), at<double>(fws, p.Lsc),
                 Lv == 0 ? B0 : at<double>(sws, p.lv.back().Bn), at<double>(sws, p.Yc),
                 Lv == 0 ? X0 : at<double>(sws, p.lv.back().Xn), (int)p.Mc, np, d, 0};
     BDS_TRY(launch_coarse_solve(c, nullptr, nullptr, 1, (d + 15) / 16, st));
     for (int l = Lv - 1; l >= 0; --l)
-        BDS_TRY(launch_solve_bwd<T>(recs[l], nullptr, nullptr, 1, units_sol_bwd((int)p.lv[l].M, d), np, st));
+        BDS_TRY(launch_solve_bwd<T>(recs[l], nullptr, nullptr, 1, units_sol_bwd((int)p.lv[l].M, d), np, p.tl, st));
     return BDS_OK;
 }
 

@@ -35,12 +35,24 @@ struct BatchPlan {
     int prec = BDS_F64;
     int nlev = 0;                 // deepest recursion over the batch
     std::vector<SysPlan> sys;     // offsets relative to the workspace start
-    // systems are grouped by padded block size np (one launch per group, so that
-    // each group runs the tiling of its own np): the distinct np in increasing
-    // order, and the number of systems of each group that reach each level
-    std::vector<int> nps;
+    // systems are grouped by padded block size np and tile shapes (one launch per
+    // kernel, level and group, so that each group runs its own tiling): the
+    // distinct groups in increasing order, and the number of systems of each
+    // group that reach each level
+    struct Group {
+        int np;
+        Tiling tl;
+        bool operator<(const Group& o) const { return np != o.np ? np < o.np : tl < o.tl; }
+        bool operator==(const Group& o) const { return np == o.np && tl == o.tl; }
+    };
+    std::vector<Group> groups;
     std::vector<std::vector<int64_t>> lvcnt;   // [level][group]
-    int group(int np) const { return (int)(std::lower_bound(nps.begin(), nps.end(), np) - nps.begin()); }
+    int group(const SysPlan& p) const
+    {
+        const Group key{(int)p.np, p.tl};
+        return (int)(std::lower_bound(groups.begin(), groups.end(), key) - groups.begin());
+    }
+    bool in_group(const SysPlan& p, const Group& g) const { return (int)p.np == g.np && p.tl == g.tl; }
     size_t ftab = 0, ftab_bytes = 0;   // factor table region
     size_t stab = 0, stab_bytes = 0;   // solve table region (solve core)
     size_t rtab = 0, rtab_bytes = 0;   // refinement / packing table region
@@ -72,16 +84,16 @@ int make_batch_plan(int64_t K, const bds_desc* descs, BatchPlan& bp)
         f += p.factor_bytes;
         s += p.solve_bytes;
         bp.nlev = std::max<int>(bp.nlev, (int)p.lv.size());
-        bp.nps.push_back((int)p.np);
+        bp.groups.push_back(BatchPlan::Group{(int)p.np, p.tl});
         bp.sys.push_back(std::move(p));
     }
-    std::sort(bp.nps.begin(), bp.nps.end());
-    bp.nps.erase(std::unique(bp.nps.begin(), bp.nps.end()), bp.nps.end());
-    const size_t G = bp.nps.size();
+    std::sort(bp.groups.begin(), bp.groups.end());
+    bp.groups.erase(std::unique(bp.groups.begin(), bp.groups.end()), bp.groups.end());
+    const size_t G = bp.groups.size();
     bp.lvcnt.assign((size_t)bp.nlev, std::vector<int64_t>(G, 0));
     std::vector<int64_t> gcnt(G, 0);
     for (const SysPlan& p : bp.sys) {
-        const int g = bp.group((int)p.np);
+        const int g = bp.group(p);
         gcnt[g] += 1;
         for (size_t l = 0; l < p.lv.size(); ++l) bp.lvcnt[l][g] += 1;
     }
@@ -192,6 +204,7 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
     }
     struct LevelTab {
         int level, np;
+        Tiling tl;
         const void* recs;
         const int64_t *sd, *sc, *ss;
         int64_t td, tc, ts;
@@ -199,15 +212,17 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
     };
     std::vector<LevelTab> lt;
     for (int l = 0; l < bp.nlev; ++l) {
-        for (const int np : bp.nps) {
+        for (const auto& grp : bp.groups) {
             std::vector<int> members;
             for (int k = 0; k < K; ++k)
-                if ((int)bp.sys[k].lv.size() > l && (int)bp.sys[k].np == np) members.push_back(k);
+                if ((int)bp.sys[k].lv.size() > l && bp.in_group(bp.sys[k], grp)) members.push_back(k);
             if (members.empty()) continue;
+            const int np = grp.np;
             lt.push_back(LevelTab{});
             LevelTab& L = lt.back();
             L.level = l;
             L.np = np;
+            L.tl = grp.tl;
             L.cnt = (int)members.size();
             const size_t m = members.size();
             // level 0 reads the FP64 inputs (or their padded copies), deeper levels the
@@ -238,10 +253,10 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
                 L.recs = dev;
             }
             auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
-            constexpr int prec = PrecOf<C>::value;
+            const Tiling tl = grp.tl;
             if (!fill_prefix(tab, m, &L.sd, [&](size_t i) { return units_fac_diag(M_of(i)); }, L.td) ||
-                !fill_prefix(tab, m, &L.sc, [&](size_t i) { return units_fac_couple(M_of(i), np, prec); }, L.tc) ||
-                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_fac_schur(M_of(i), np, prec); }, L.ts))
+                !fill_prefix(tab, m, &L.sc, [&](size_t i) { return units_fac_couple(M_of(i), np, tl.couple); }, L.tc) ||
+                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_fac_schur(M_of(i), np, tl.schur); }, L.ts))
                 return BDS_EWORKSPACE;
         }
     }
@@ -281,10 +296,10 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
     for (const LevelTab& L : lt) {
         if (L.level == 0) {
             BDS_TRY(launch_factor_level<C, double>(FacLv<T, double>{}, static_cast<const FacLv<T, double>*>(L.recs),
-                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np, st));
+                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np, L.tl, st));
         } else {
             BDS_TRY(launch_factor_level<C, T>(FacLv<T, T>{}, static_cast<const FacLv<T, T>*>(L.recs), L.sd, L.sc,
-                                              L.ss, L.cnt, L.td, L.tc, L.ts, L.np, st));
+                                              L.ss, L.cnt, L.td, L.tc, L.ts, L.np, L.tl, st));
         }
     }
     int np0 = 16, np1 = 16;
@@ -303,6 +318,7 @@ int solve_core_batched(const BatchPlan& bp, const std::vector<int>& act, const v
     Table tab(sws, bp.stab, bp.stab_bytes);
     struct LevelTab {
         int level, np;
+        Tiling tl;
         const SolLv<T>* recs;
         const int64_t *si, *ss, *sb;
         int64_t ti, ts, tb;
@@ -310,15 +326,17 @@ int solve_core_batched(const BatchPlan& bp, const std::vector<int>& act, const v
     };
     std::vector<LevelTab> lt;
     for (int l = 0; l < bp.nlev; ++l) {
-        for (const int np : bp.nps) {
+        for (const auto& grp : bp.groups) {
             std::vector<int> members;
             for (int k : act)
-                if ((int)bp.sys[k].lv.size() > l && (int)bp.sys[k].np == np) members.push_back(k);
+                if ((int)bp.sys[k].lv.size() > l && bp.in_group(bp.sys[k], grp)) members.push_back(k);
             if (members.empty()) continue;
+            const int np = grp.np;
             lt.push_back(LevelTab{});
             LevelTab& L = lt.back();
             L.level = l;
             L.np = np;
+            L.tl = grp.tl;
             L.cnt = (int)members.size();
             const size_t m = members.size();
             SolLv<T>* h = tab.take<SolLv<T>>(m, &L.recs);
@@ -334,8 +352,8 @@ int solve_core_batched(const BatchPlan& bp, const std::vector<int>& act, const v
             }
             auto M_of = [&](size_t i) { return (int)bp.sys[members[i]].lv[l].M; };
             auto d_of = [&](size_t i) { return (int)bp.sys[members[i]].d; };
-            if (!fill_prefix(tab, m, &L.si, [&](size_t i) { return units_sol_fwd_int(M_of(i), np, d_of(i)); }, L.ti) ||
-                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_sol_fwd_sep(M_of(i), np, d_of(i)); }, L.ts) ||
+            if (!fill_prefix(tab, m, &L.si, [&](size_t i) { return units_sol_fwd_int(M_of(i), np, d_of(i), L.tl.sol); }, L.ti) ||
+                !fill_prefix(tab, m, &L.ss, [&](size_t i) { return units_sol_fwd_sep(M_of(i), np, d_of(i), L.tl.sol); }, L.ts) ||
                 !fill_prefix(tab, m, &L.sb, [&](size_t i) { return units_sol_bwd(M_of(i), d_of(i)); }, L.tb))
                 return BDS_EWORKSPACE;
         }
@@ -358,10 +376,10 @@ int solve_core_batched(const BatchPlan& bp, const std::vector<int>& act, const v
         return BDS_EWORKSPACE;
     BDS_TRY(tab.upload(st));
     for (const LevelTab& L : lt)
-        BDS_TRY(launch_solve_fwd<T>(SolLv<T>{}, L.recs, L.si, L.ss, L.cnt, L.ti, L.ts, L.np, st));
+        BDS_TRY(launch_solve_fwd<T>(SolLv<T>{}, L.recs, L.si, L.ss, L.cnt, L.ti, L.ts, L.np, L.tl, st));
     BDS_TRY(launch_coarse_solve(CoarseSol{}, cdev, cstart, (int)m, ctot, st));
     for (auto it = lt.rbegin(); it != lt.rend(); ++it)
-        BDS_TRY(launch_solve_bwd<T>(SolLv<T>{}, it->recs, it->sb, it->cnt, it->tb, it->np, st));
+        BDS_TRY(launch_solve_bwd<T>(SolLv<T>{}, it->recs, it->sb, it->cnt, it->tb, it->np, it->tl, st));
     return BDS_OK;
 }
 
@@ -427,10 +445,11 @@ int refined_solve_batched(const BatchPlan& bp, const void* fws, const std::vecto
             int cnt, np;
         };
         std::vector<ResTab> rts;
-        for (const int np : bp.nps) {
+        for (const auto& grp : bp.groups) {
+            const int np = grp.np;
             std::vector<int> members;
             for (int k : act)
-                if ((int)bp.sys[k].np == np) members.push_back(k);
+                if (bp.in_group(bp.sys[k], grp)) members.push_back(k);
             if (members.empty()) continue;
             ResTab r{nullptr, nullptr, 0, (int)members.size(), np};
             ResidArgs* rh = tab.take<ResidArgs>(members.size(), &r.recs);

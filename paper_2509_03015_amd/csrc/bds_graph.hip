@@ -40,6 +40,7 @@ void GraphKey::add_desc(const bds_desc& d)
     add((uint64_t)d.n);
     add((uint64_t)d.d);
     add((uint64_t)(uint32_t)d.prec | ((uint64_t)(uint32_t)d.nstar << 32));
+    add((uint64_t)(uint32_t)d.tiles);
 }
 
 bool GraphKey::operator==(const GraphKey& o) const

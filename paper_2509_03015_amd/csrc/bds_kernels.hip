@@ -69,42 +69,81 @@ template <typename S> struct Many {
 };
 
 int tile_r(int np) { return (np % 32 == 0) ? 2 : 1; }
-bool fac_tiles_wg(int np) { return np % 64 == 0; }
-// Macro tile of the work-group tile products by compute precision.  FP64: 64
-// (four work-groups per CU keep enough HBM reads in flight).  The FP32 and BF16
-// MFMAs take 1/2 and 1/8 the cycles of FP64 per k step, so a 64-wide tile spends
-// relatively more time per chunk on loads, LDS staging and the barrier; 128-wide
-// tiles halve that overhead per flop where np allows: for both products in BF16,
-// for the couplings in FP32 (measured: the FP32 Schur update is faster with 64).
+// Library rule for the tile shapes.  Couplings and Schur updates of blocks that
+// are a multiple of 64 run as work-group tile products; the macro tile depends
+// on the compute precision: FP64 64 (four work-groups per CU keep enough HBM
+// reads in flight); the FP32 and BF16 MFMAs take 1/2 and 1/8 the cycles of
+// FP64 per k step, so a 64-wide tile spends relatively more time per chunk on
+// loads, LDS staging and the barrier, and 128-wide tiles halve that overhead
+// per flop where np allows: both products in BF16, the couplings in FP32
+// (measured: the FP32 Schur update is faster with 64).  Other block sizes use
+// wave tiles, 32 x 32 where they divide np.
 static_assert(PrecOf<double>::value == BDS_F64 && PrecOf<float>::value == BDS_F32 &&
                   PrecOf<bf16x>::value == BDS_BF16,
               "precision codes of the compute tags");
-int fac_mt_couple(int np, int prec) { return (prec != BDS_F64 && np % 128 == 0) ? 128 : 64; }
-int fac_mt_schur(int np, int prec) { return (prec == BDS_BF16 && np % 128 == 0) ? 128 : 64; }
+static int wave_rule(int np) { return np % 32 == 0 ? BDS_TILE_W32 : BDS_TILE_W16; }
+static int couple_rule(int np, int prec)
+{
+    if (np % 64) return wave_rule(np);
+    return (prec != BDS_F64 && np % 128 == 0) ? BDS_TILE_G128 : BDS_TILE_G64;
+}
+static int schur_rule(int np, int prec)
+{
+    if (np % 64) return wave_rule(np);
+    return (prec == BDS_BF16 && np % 128 == 0) ? BDS_TILE_G128 : BDS_TILE_G64;
+}
+static bool tile_fits(int code, int np)
+{
+    switch (code) {
+    case BDS_TILE_W16: return true;
+    case BDS_TILE_W32: return np % 32 == 0;
+    case BDS_TILE_G64: return np % 64 == 0;
+    case BDS_TILE_G128: return np % 128 == 0;
+    default: return false;
+    }
+}
+bool resolve_tiling(int np, int prec, int32_t tiles, Tiling& t)
+{
+    if (tiles & ~0xFFF) return false;
+    const int c = tiles & 15, sc = (tiles >> 4) & 15, v = (tiles >> 8) & 15;
+    t.couple = c ? c : couple_rule(np, prec);
+    t.schur = sc ? sc : schur_rule(np, prec);
+    t.sol = v ? v : wave_rule(np);
+    return tile_fits(t.couple, np) && tile_fits(t.schur, np) && tile_fits(t.sol, np) &&
+           (t.sol == BDS_TILE_W16 || t.sol == BDS_TILE_W32);
+}
+std::vector<int> tile_choices(int np, bool solve)
+{
+    std::vector<int> v;
+    for (int code : {BDS_TILE_W16, BDS_TILE_W32, BDS_TILE_G64, BDS_TILE_G128})
+        if (tile_fits(code, np) && (!solve || code <= BDS_TILE_W32)) v.push_back(code);
+    return v;
+}
+static inline int wave_r(int code) { return code == BDS_TILE_W32 ? 2 : 1; }
 
 static int64_t units_fac_couple_wg(int M, int np, int MT);
 static int64_t units_fac_schur_wg(int M, int np, int MT);
 int64_t units_fac_diag(int M) { return M / 2; }
-int64_t units_fac_couple(int M, int np, int prec)
+int64_t units_fac_couple(int M, int np, int code)
 {
-    if (fac_tiles_wg(np)) return units_fac_couple_wg(M, np, fac_mt_couple(np, prec));
-    const int tp = np / (16 * tile_r(np));
+    if (code >= BDS_TILE_G64) return units_fac_couple_wg(M, np, code == BDS_TILE_G128 ? 128 : 64);
+    const int tp = np / (16 * wave_r(code));
     return (int64_t)(M / 2) * 2 * tp * tp;
 }
-int64_t units_fac_schur(int M, int np, int prec)
+int64_t units_fac_schur(int M, int np, int code)
 {
-    if (fac_tiles_wg(np)) return units_fac_schur_wg(M, np, fac_mt_schur(np, prec));
-    const int tp = np / (16 * tile_r(np));
+    if (code >= BDS_TILE_G64) return units_fac_schur_wg(M, np, code == BDS_TILE_G128 ? 128 : 64);
+    const int tp = np / (16 * wave_r(code));
     return (int64_t)((M + 1) / 2) * (tp * (tp + 1) / 2 + tp * tp);
 }
 static inline int dchunks(int d) { return (d + 15) / 16; }
-int64_t units_sol_fwd_int(int M, int np, int d)
+int64_t units_sol_fwd_int(int M, int np, int d, int code)
 {
-    return (int64_t)(M / 2) * (np / (16 * tile_r(np))) * dchunks(d);
+    return (int64_t)(M / 2) * (np / (16 * wave_r(code))) * dchunks(d);
 }
-int64_t units_sol_fwd_sep(int M, int np, int d)
+int64_t units_sol_fwd_sep(int M, int np, int d, int code)
 {
-    return (int64_t)((M + 1) / 2) * (np / (16 * tile_r(np))) * dchunks(d);
+    return (int64_t)((M + 1) / 2) * (np / (16 * wave_r(code))) * dchunks(d);
 }
 int64_t units_sol_bwd(int M, int d) { return (int64_t)(M / 2) * dchunks(d); }
 int64_t units_resid(int N, int np, int d) { return (int64_t)N * (np / (16 * tile_r(np))) * dchunks(d); }
@@ -822,7 +861,7 @@ template <typename C, typename In>
 hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                const FacLv<typename Stor<C>::type, In>* tab, const int64_t* sd,
                                const int64_t* sc, const int64_t* ss, int K, int64_t td, int64_t tc,
-                               int64_t ts, int np, hipStream_t st)
+                               int64_t ts, int np, const Tiling& tl, hipStream_t st)
 {
     hipError_t e = with_table(one, tab, sd, K, td, [&](auto t) {
         return dispatch_nt(np, [&](auto nt) {
@@ -832,35 +871,23 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
         });
     });
     if (e != hipSuccess) return e;
-    if (fac_tiles_wg(np)) {
-        // work-group tile products (macro tile by precision, see fac_mt_couple)
-        constexpr int prec = PrecOf<C>::value;
-        e = with_table(one, tab, sc, K, tc, [&](auto t) {
-            if (fac_mt_couple(np, prec) == 128)
-                BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 128><<<(unsigned)tc, 256, 0, st>>>(t));
-            else
-                BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64><<<(unsigned)tc, 256, 0, st>>>(t));
-            return hipGetLastError();
-        });
-        if (e != hipSuccess) return e;
-        return with_table(one, tab, ss, K, ts, [&](auto t) {
-            if (fac_mt_schur(np, prec) == 128)
-                BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 128><<<(unsigned)ts, 256, 0, st>>>(t));
-            else
-                BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64><<<(unsigned)ts, 256, 0, st>>>(t));
-            return hipGetLastError();
-        });
-    }
-    const bool r2 = tile_r(np) == 2;
     e = with_table(one, tab, sc, K, tc, [&](auto t) {
-        if (r2) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(t));
-        else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(t));
+        switch (tl.couple) {
+        case BDS_TILE_G128: BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 128><<<(unsigned)tc, 256, 0, st>>>(t)); break;
+        case BDS_TILE_G64: BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64><<<(unsigned)tc, 256, 0, st>>>(t)); break;
+        case BDS_TILE_W32: BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(t)); break;
+        default: BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(t)); break;
+        }
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
     return with_table(one, tab, ss, K, ts, [&](auto t) {
-        if (r2) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(t));
-        else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(t));
+        switch (tl.schur) {
+        case BDS_TILE_G128: BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 128><<<(unsigned)ts, 256, 0, st>>>(t)); break;
+        case BDS_TILE_G64: BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64><<<(unsigned)ts, 256, 0, st>>>(t)); break;
+        case BDS_TILE_W32: BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(t)); break;
+        default: BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(t)); break;
+        }
         return hipGetLastError();
     });
 }
@@ -892,9 +919,9 @@ hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* t
 
 template <typename T>
 hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab, const int64_t* si, const int64_t* ss,
-                            int K, int64_t ti, int64_t ts, int np, hipStream_t st)
+                            int K, int64_t ti, int64_t ts, int np, const Tiling& tl, hipStream_t st)
 {
-    const bool r2 = tile_r(np) == 2;
+    const bool r2 = tl.sol == BDS_TILE_W32;
     hipError_t e = with_table(one, tab, si, K, ti, [&](auto t) {
         if (r2) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2><<<grid_waves(ti), 256, 0, st>>>(t));
         else BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(t));
@@ -910,11 +937,11 @@ hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab, const int6
 
 template <typename T>
 hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab, const int64_t* sb, int K, int64_t tb,
-                            int np, hipStream_t st)
+                            int np, const Tiling& tl, hipStream_t st)
 {
     // a work-group's four waves share the np / (16 R) row tiles of one interior:
     // 32-row tiles only where that still leaves a tile per wave
-    const int R = (tile_r(np) == 2 && np >= 128) ? 2 : 1;
+    const int R = (tl.sol == BDS_TILE_W32 && np >= 128) ? 2 : 1;
     const unsigned threads = 64u * (unsigned)std::min(4, np / (16 * R));
     const size_t lds = (size_t)np * 16 * sizeof(double);
     return with_table(one, tab, sb, K, tb, [&](auto t) {
@@ -1035,7 +1062,7 @@ hipError_t launch_set_refine_info(bds_info* info, int iters, int converged, hipS
 #define BDS_INST_FAC(C, In)                                                                                   \
     template hipError_t launch_factor_level<C, In>(                                                           \
         const FacLv<Stor<C>::type, In>&, const FacLv<Stor<C>::type, In>*, const int64_t*, const int64_t*,    \
-        const int64_t*, int, int64_t, int64_t, int64_t, int, hipStream_t);
+        const int64_t*, int, int64_t, int64_t, int64_t, int, const Tiling&, hipStream_t);
 BDS_INST_FAC(double, double)
 BDS_INST_FAC(float, double)
 BDS_INST_FAC(float, float)
@@ -1046,12 +1073,12 @@ template hipError_t launch_coarse_factor<double>(const CoarseFac<double>&, const
 template hipError_t launch_coarse_factor<float>(const CoarseFac<float>&, const CoarseFac<float>*, int, int,
                                                 hipStream_t);
 template hipError_t launch_solve_fwd<double>(const SolLv<double>&, const SolLv<double>*, const int64_t*,
-                                             const int64_t*, int, int64_t, int64_t, int, hipStream_t);
+                                             const int64_t*, int, int64_t, int64_t, int, const Tiling&, hipStream_t);
 template hipError_t launch_solve_fwd<float>(const SolLv<float>&, const SolLv<float>*, const int64_t*,
-                                            const int64_t*, int, int64_t, int64_t, int, hipStream_t);
+                                            const int64_t*, int, int64_t, int64_t, int, const Tiling&, hipStream_t);
 template hipError_t launch_solve_bwd<double>(const SolLv<double>&, const SolLv<double>*, const int64_t*, int,
-                                             int64_t, int, hipStream_t);
+                                             int64_t, int, const Tiling&, hipStream_t);
 template hipError_t launch_solve_bwd<float>(const SolLv<float>&, const SolLv<float>*, const int64_t*, int,
-                                            int64_t, int, hipStream_t);
+                                            int64_t, int, const Tiling&, hipStream_t);
 
 }  // namespace bds

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/bds.h"
 #include "bds_device.hpp"
 
@@ -94,22 +96,33 @@ struct PackRec {
     int n, np, cols, mode;  // cols: d for right-hand sides (unused for matrix blocks)
 };
 
+// Tile shapes of one system's reduction levels (BDS_TILE_* codes of bds.h),
+// resolved from bds_desc::tiles with the library's rule for the zero fields.
+struct Tiling {
+    int couple = BDS_TILE_W16;  // coupling products
+    int schur = BDS_TILE_W16;   // Schur updates
+    int sol = BDS_TILE_W16;     // solve sweeps (wave tiles)
+    bool operator==(const Tiling& o) const { return couple == o.couple && schur == o.schur && sol == o.sol; }
+    bool operator<(const Tiling& o) const
+    {
+        return couple != o.couple ? couple < o.couple : schur != o.schur ? schur < o.schur : sol < o.sol;
+    }
+};
+// false if a field is not a known code or does not fit the padded block size np.
+bool resolve_tiling(int np, int prec, int32_t tiles, Tiling& out);
+// Tile codes that fit np for one field (couple/schur: all; solve: wave tiles).
+std::vector<int> tile_choices(int np, bool solve);
+
 // Work-unit counts per record (waves for wave kernels, work-groups otherwise).
-// The tiling depends on the block size np only: wave kernels compute
-// (16R) x (16R) output tiles with R = tile_r(np); blocks that are a multiple
-// of 64 (fac_tiles_wg) use the work-group tile products for the couplings and
-// Schur updates, whose macro tile also depends on the compute precision prec
-// (BDS_F64, BDS_F32, BDS_BF16).  A table passed to a launcher holds records of
-// one np.
+// tile_r(np) is the wave tile factor (a wave computes (16R) x (16R) outputs)
+// of the kernels that are not tuned (residual, coarse system).  A table
+// passed to a launcher holds records of one np and one Tiling.
 int tile_r(int np);
-bool fac_tiles_wg(int np);
 int64_t units_fac_diag(int M);
-int fac_mt_couple(int np, int prec);
-int fac_mt_schur(int np, int prec);
-int64_t units_fac_couple(int M, int np, int prec);
-int64_t units_fac_schur(int M, int np, int prec);
-int64_t units_sol_fwd_int(int M, int np, int d);
-int64_t units_sol_fwd_sep(int M, int np, int d);
+int64_t units_fac_couple(int M, int np, int code);
+int64_t units_fac_schur(int M, int np, int code);
+int64_t units_sol_fwd_int(int M, int np, int d, int code);
+int64_t units_sol_fwd_sep(int M, int np, int d, int code);
 int64_t units_sol_bwd(int M, int d);
 int64_t units_resid(int N, int np, int d);
 
@@ -121,7 +134,7 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                const FacLv<typename Stor<C>::type, In>* tab_dev,
                                const int64_t* start_diag, const int64_t* start_couple,
                                const int64_t* start_schur, int K, int64_t tot_diag,
-                               int64_t tot_couple, int64_t tot_schur, int np, hipStream_t st);
+                               int64_t tot_couple, int64_t tot_schur, int np, const Tiling& tl, hipStream_t st);
 
 template <typename In>
 hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* tab_dev, int K, int np_max,
@@ -130,11 +143,11 @@ hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* t
 template <typename T>
 hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab_dev, const int64_t* start_int,
                             const int64_t* start_sep, int K, int64_t tot_int, int64_t tot_sep,
-                            int np, hipStream_t st);
+                            int np, const Tiling& tl, hipStream_t st);
 
 template <typename T>
 hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab_dev, const int64_t* start,
-                            int K, int64_t tot, int np, hipStream_t st);
+                            int K, int64_t tot, int np, const Tiling& tl, hipStream_t st);
 
 hipError_t launch_coarse_solve(const CoarseSol& one, const CoarseSol* tab_dev, const int64_t* start,
                                int K, int64_t tot, hipStream_t st);

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/bds.h"
+#include "bds_kernels.hpp"
 
 namespace bds {
 
@@ -60,6 +61,7 @@ struct SysPlan {
     int max_refine = kDefaultMaxRefine;
     double refine_tol = kDefaultRefineTol;
     size_t esize = 8;
+    Tiling tl;            // tile shapes of the reduction levels
     bool packed = false;  // n % 16 != 0: user arrays are copied into padded buffers
     std::vector<LevelPlan> lv;
     int64_t Mc = 0;       // blocks of the coarse system

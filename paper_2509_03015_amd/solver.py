@@ -2,6 +2,7 @@
 
     F = factor(Ad, As, prec="f64")      # recursive factorisation (the paper's Alg. 4)
     X = F.solve(B)                      # recursive solve (Alg. 5-7), refined if prec != "f64"
+    F.tune(B)                           # autotuner: crossover nstar and tile shapes for this shape
     X = solve(Ad, As, B)                # differentiable: torch.autograd.Function
 
 Shapes (float64, CUDA/HIP device, C-contiguous): Ad (N, n, n) with only the
@@ -58,7 +59,7 @@ class Factor:
     """Factor hierarchy of one SPD block-tridiagonal matrix, held in a device workspace."""
 
     def __init__(self, Ad: torch.Tensor, As: torch.Tensor | None, prec: str = "f64", nstar: int = 0,
-                 check: bool = True):
+                 check: bool = True, tiles: int = 0):
         if Ad.dim() != 3:
             raise ValueError("Ad must have shape (N, n, n)")
         N, n, _ = Ad.shape
@@ -69,16 +70,19 @@ class Factor:
         self.N, self.n = int(N), int(n)
         self.prec = prec
         self.nstar = int(nstar)
+        self.tiles = int(tiles)
         self.Ad, self.As = Ad, (As if N > 1 else None)
         self._solve_ws = {}
-        desc = self._desc(1)
-        rc, fbytes, _ = bb.workspace_size(desc)
+        self.info_t = torch.zeros(8, dtype=torch.int32, device=self.device)
+        self._alloc_factor()
+        self.refactor(check=check)
+
+    def _alloc_factor(self):
+        rc, fbytes, _ = bb.workspace_size(self._desc(1))
         if rc != bb.BDS_OK:
             raise BdsError(rc, "bds_workspace_size")
         self.fbytes = fbytes
         self.fws = torch.empty(max(fbytes, 1), dtype=torch.uint8, device=self.device)
-        self.info_t = torch.zeros(8, dtype=torch.int32, device=self.device)
-        self.refactor(check=check)
 
     def refactor(self, check: bool = False):
         """Run bds_factor again on the same Ad/As into the existing workspace (no allocation)."""
@@ -93,8 +97,8 @@ class Factor:
     def _desc(self, d: int, max_refine: int = 0, refine_tol: float = 0.0) -> bb.BdsDesc:
         if self.prec not in PRECISIONS:
             raise ValueError(f"prec must be one of {list(PRECISIONS)}")
-        return bb.BdsDesc(self.N, self.n, int(d), PRECISIONS[self.prec], self.nstar, int(max_refine), 0,
-                          float(refine_tol))
+        return bb.BdsDesc(self.N, self.n, int(d), PRECISIONS[self.prec], self.nstar, int(max_refine),
+                          self.tiles, float(refine_tol))
 
     def info(self) -> dict:
         """Synchronise and read the device info record of the last call."""
@@ -135,6 +139,35 @@ class Factor:
             self.check("bds_solve")
         return X
 
+    def tune(self, B: torch.Tensor, reps: int = 3, max_refine: int = 0, refine_tol: float = 0.0) -> dict:
+        """Run the library's autotuner (bds_tune) on this system with right-hand side B.
+
+        The fields left to the library (nstar == 0, zero tile fields) are searched; the factor is then
+        rebuilt with the winner, which later solves use.  Returns the chosen nstar and tile shapes.
+        """
+        d = int(B.shape[2])
+        _check_tensor(B, "B", (self.N, self.n, d), self.device)
+        desc = self._desc(d, max_refine, refine_tol)
+        rc, fbytes, sbytes = bb.tune_workspace_size(desc)
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_tune_workspace_size")
+        fws = torch.empty(max(fbytes, 1), dtype=torch.uint8, device=self.device)
+        sws = torch.empty(max(sbytes, 1), dtype=torch.uint8, device=self.device)
+        X = torch.empty_like(B)
+        best = bb.BdsDesc()
+        rc = bb.load().bds_tune(ctypes.byref(desc), _ptr(self.Ad), _ptr(self.As), _ptr(B), _ptr(X), _ptr(fws),
+                                fbytes, _ptr(sws), sbytes, _ptr(self.info_t), int(reps),
+                                _stream_handle(self.device), ctypes.byref(best))
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_tune")
+        self.check("bds_tune")
+        del fws, sws
+        self.nstar, self.tiles = int(best.nstar), int(best.tiles)
+        self._solve_ws = {}
+        self._alloc_factor()
+        self.refactor(check=True)
+        return {"nstar": self.nstar, "tiles": self.tiles, **bb.tiles_fields(self.tiles)}
+
     def backward(self, X: torch.Tensor, dX: torch.Tensor, check: bool = True):
         """Gradients (dAd, dAs, dB) of a loss with dL/dX = dX, for X = A^-1 B."""
         d = int(X.shape[2])
@@ -162,12 +195,15 @@ def _ptr_array(ts):
 class BatchedFactor:
     """Factor hierarchies of K independent systems of uneven size, built by one launch per kernel and level."""
 
-    def __init__(self, Ads, Ass, prec: str = "f64", nstar: int = 0, check: bool = True):
+    def __init__(self, Ads, Ass, prec: str = "f64", nstar: int = 0, check: bool = True, tiles=None):
         if len(Ads) != len(Ass) or len(Ads) == 0:
             raise ValueError("need equally many (>= 1) Ad and As tensors")
         self.K = len(Ads)
         self.device = Ads[0].device
         self.prec, self.nstar = prec, int(nstar)
+        self.tiles = [0] * self.K if tiles is None else [int(t) for t in tiles]
+        if len(self.tiles) != self.K:
+            raise ValueError("tiles needs one entry per system")
         self.shapes = []
         for k, (Ad, As) in enumerate(zip(Ads, Ass)):
             if Ad.dim() != 3:
@@ -180,25 +216,57 @@ class BatchedFactor:
         self.Ads = list(Ads)
         self.Ass = [As if N > 1 else None for As, (N, _) in zip(Ass, self.shapes)]
         self._solve_ws = {}
-        descs = self._descs([1] * self.K)
+        self.info_t = torch.zeros((self.K, 8), dtype=torch.int32, device=self.device)
+        self._Ad_p = _ptr_array(self.Ads)
+        self._As_p = _ptr_array(self.Ass)
+        self._alloc_factor()
+        self.refactor(check=check)
+
+    def _sizes(self, descs):
         f = ctypes.c_size_t(0)
         sb = ctypes.c_size_t(0)
         rc = bb.load().bds_batched_workspace_size(self.K, descs, ctypes.byref(f), ctypes.byref(sb))
         if rc != bb.BDS_OK:
             raise BdsError(rc, "bds_batched_workspace_size")
-        self.fbytes = f.value
+        return f.value, sb.value
+
+    def _alloc_factor(self):
+        self.fbytes, _ = self._sizes(self._descs([1] * self.K))
         self.fws = torch.empty(max(self.fbytes, 1), dtype=torch.uint8, device=self.device)
-        self.info_t = torch.zeros((self.K, 8), dtype=torch.int32, device=self.device)
-        self._Ad_p = _ptr_array(self.Ads)
-        self._As_p = _ptr_array(self.Ass)
-        self.refactor(check=check)
 
     def _descs(self, ds, max_refine: int = 0, refine_tol: float = 0.0):
         arr = (bb.BdsDesc * self.K)()
         for k, ((N, n), d) in enumerate(zip(self.shapes, ds)):
-            arr[k] = bb.BdsDesc(N, n, int(d), PRECISIONS[self.prec], self.nstar, int(max_refine), 0,
+            arr[k] = bb.BdsDesc(N, n, int(d), PRECISIONS[self.prec], self.nstar, int(max_refine), self.tiles[k],
                                 float(refine_tol))
         return arr
+
+    def tune(self, Bs, reps: int = 3, max_refine: int = 0, refine_tol: float = 0.0) -> dict:
+        """Run the batched autotuner (bds_tune_batched): tile shapes per padded block size, chosen by
+        timing factor + solve of the whole batch.  The factor is rebuilt with the winner.  Returns
+        {np: {"couple": .., "schur": .., "solve": ..}}."""
+        ds = [int(B.shape[2]) for B in Bs]
+        descs = self._descs(ds, max_refine, refine_tol)
+        fbytes, sbytes = self._sizes(descs)
+        fws = torch.empty(max(fbytes, 1), dtype=torch.uint8, device=self.device)
+        sws = torch.empty(max(sbytes, 1), dtype=torch.uint8, device=self.device)
+        Xs = [torch.empty_like(B) for B in Bs]
+        best = (bb.BdsDesc * self.K)()
+        rc = bb.load().bds_tune_batched(self.K, descs, self._Ad_p, self._As_p, _ptr_array(Bs), _ptr_array(Xs),
+                                        _ptr(fws), fbytes, _ptr(sws), sbytes, _ptr(self.info_t), int(reps),
+                                        _stream_handle(self.device), best)
+        if rc != bb.BDS_OK:
+            raise BdsError(rc, "bds_tune_batched")
+        self.check("bds_tune_batched")
+        del fws, sws
+        self.tiles = [int(best[k].tiles) for k in range(self.K)]
+        self._solve_ws = {}
+        self._alloc_factor()
+        self.refactor(check=True)
+        out = {}
+        for (N, n), t in zip(self.shapes, self.tiles):
+            out[(n + 15) // 16 * 16] = bb.tiles_fields(t)
+        return out
 
     def refactor(self, check: bool = False):
         descs = self._descs([1] * self.K)
@@ -236,12 +304,8 @@ class BatchedFactor:
         key = tuple(ds)
         ws = self._solve_ws.get(key)
         if ws is None:
-            f = ctypes.c_size_t(0)
-            sb = ctypes.c_size_t(0)
-            rc = bb.load().bds_batched_workspace_size(self.K, descs, ctypes.byref(f), ctypes.byref(sb))
-            if rc != bb.BDS_OK:
-                raise BdsError(rc, "bds_batched_workspace_size")
-            ws = torch.empty(max(sb.value, 1), dtype=torch.uint8, device=self.device)
+            _, sb = self._sizes(descs)
+            ws = torch.empty(max(sb, 1), dtype=torch.uint8, device=self.device)
             self._solve_ws[key] = ws
         rc = bb.load().bds_solve_batched(self.K, descs, _ptr(self.fws), self.fbytes, self._Ad_p, self._As_p,
                                          _ptr_array(Bs), _ptr_array(Xs), _ptr(ws), ws.numel(), _ptr(self.info_t),
@@ -253,13 +317,13 @@ class BatchedFactor:
         return Xs
 
 
-def factor_batched(Ads, Ass, prec: str = "f64", nstar: int = 0, check: bool = True) -> BatchedFactor:
-    return BatchedFactor(Ads, Ass, prec=prec, nstar=nstar, check=check)
+def factor_batched(Ads, Ass, prec: str = "f64", nstar: int = 0, check: bool = True, tiles=None) -> BatchedFactor:
+    return BatchedFactor(Ads, Ass, prec=prec, nstar=nstar, check=check, tiles=tiles)
 
 
 def factor(Ad: torch.Tensor, As: torch.Tensor | None, prec: str = "f64", nstar: int = 0,
-           check: bool = True) -> Factor:
-    return Factor(Ad, As, prec=prec, nstar=nstar, check=check)
+           check: bool = True, tiles: int = 0) -> Factor:
+    return Factor(Ad, As, prec=prec, nstar=nstar, check=check, tiles=tiles)
 
 
 class _Solve(torch.autograd.Function):

@@ -40,8 +40,8 @@ def test_library_exports_every_header_symbol(lib):
     assert b"gfx950" in lib.bds_version()
 
 
-def desc(N=64, n=16, d=1, prec=0, nstar=0, max_refine=0, reserved=0, tol=0.0):
-    return bb.BdsDesc(N, n, d, prec, nstar, max_refine, reserved, tol)
+def desc(N=64, n=16, d=1, prec=0, nstar=0, max_refine=0, tiles=0, tol=0.0):
+    return bb.BdsDesc(N, n, d, prec, nstar, max_refine, tiles, tol)
 
 
 def test_workspace_sizes_follow_the_level_plan(lib):
@@ -69,7 +69,11 @@ def test_padding_to_multiple_of_16(lib):
 
 
 @pytest.mark.parametrize("bad", [dict(N=0), dict(n=0), dict(n=257), dict(d=0), dict(prec=7), dict(nstar=-1),
-                                 dict(max_refine=-2), dict(reserved=1), dict(tol=-1.0)])
+                                 dict(max_refine=-2), dict(tol=-1.0), dict(tiles=5), dict(tiles=1 << 12),
+                                 dict(tiles=bb.tiles(solve=bb.BDS_TILE_G64), n=64),
+                                 dict(tiles=bb.tiles(couple=bb.BDS_TILE_W32), n=16),
+                                 dict(tiles=bb.tiles(schur=bb.BDS_TILE_G64), n=32),
+                                 dict(tiles=bb.tiles(couple=bb.BDS_TILE_G128), n=64)])
 def test_invalid_descriptors_rejected(lib, bad):
     kw = dict(N=8, n=4, d=1)
     kw.update(bad)
@@ -139,3 +143,39 @@ def test_trace_enable_bounds(lib):
     assert lib.bds_trace_enable(-1) == bb.BDS_EINVAL
     assert lib.bds_trace_enable(1 << 21) == bb.BDS_EINVAL
     assert lib.bds_trace_enable(0) == bb.BDS_OK
+
+
+@pytest.mark.parametrize("n,t", [(16, bb.tiles(bb.BDS_TILE_W16, bb.BDS_TILE_W16, bb.BDS_TILE_W16)),
+                                 (32, bb.tiles(bb.BDS_TILE_W32, bb.BDS_TILE_W16, bb.BDS_TILE_W32)),
+                                 (64, bb.tiles(bb.BDS_TILE_G64, bb.BDS_TILE_W32, bb.BDS_TILE_W16)),
+                                 (128, bb.tiles(bb.BDS_TILE_G128, bb.BDS_TILE_G64, bb.BDS_TILE_W32)),
+                                 (256, bb.tiles(schur=bb.BDS_TILE_G128))])
+def test_tile_choices_that_fit_are_accepted_and_do_not_change_workspaces(lib, n, t):
+    rc, f, s = bb.workspace_size(desc(40, n, 3, tiles=t))
+    rc0, f0, s0 = bb.workspace_size(desc(40, n, 3))
+    assert rc == 0 and rc0 == 0 and (f, s) == (f0, s0)
+
+
+def test_tune_workspace_covers_every_nstar_candidate(lib):
+    rc, f, s = bb.tune_workspace_size(desc(100, 32, 2))
+    assert rc == 0
+    for ns in (1, 2, 4, 8, 16, 32, 64):
+        rc1, f1, s1 = bb.workspace_size(desc(100, 32, 2, nstar=ns))
+        assert rc1 == 0 and f1 <= f and s1 <= s
+    # a fixed nstar is not searched
+    assert bb.tune_workspace_size(desc(100, 32, 2, nstar=8))[1:] == bb.workspace_size(desc(100, 32, 2, nstar=8))[1:]
+    assert bb.tune_workspace_size(desc(0, 32, 2))[0] == bb.BDS_EINVAL
+
+
+def test_tune_rejects_bad_arguments_without_launching(lib):
+    d = desc(8, 4, 1)
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    best = bb.BdsDesc()
+    assert lib.bds_tune(ctypes.byref(d), fake, fake, fake, fake, fake, 1 << 30, fake, 1 << 30, fake, 3, null,
+                        None) == bb.BDS_EINVAL          # no output descriptor
+    assert lib.bds_tune(ctypes.byref(d), fake, fake, fake, fake, fake, 16, fake, 1 << 30, fake, 3, null,
+                        ctypes.byref(best)) == bb.BDS_EWORKSPACE
+    bad = desc(8, 4, 1, tiles=9)
+    assert lib.bds_tune(ctypes.byref(bad), fake, fake, fake, fake, fake, 1 << 30, fake, 1 << 30, fake, 3, null,
+                        ctypes.byref(best)) == bb.BDS_EINVAL

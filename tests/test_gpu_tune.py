@@ -1,0 +1,127 @@
+"""GPU parity of every tile shape and of the autotuner (bds_tune, bds_tune_batched) against the CPU oracle.
+
+Every tile choice computes the same X up to rounding, so each is held to the FP64 bar (relative error
+<= 1e-12 at kappa ~ 4); the mixed-precision cases to the refined bar (<= 1e-10, here well below).
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2509_03015_amd import _binding as bb
+from paper_2509_03015_amd import inputs
+from tests.dense import relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2509_03015_amd import solver
+    solver.bb.load()
+    return solver
+
+
+def fitting(n, solve):
+    np_ = (n + 15) // 16 * 16
+    codes = [bb.BDS_TILE_W16, bb.BDS_TILE_W32, bb.BDS_TILE_G64, bb.BDS_TILE_G128]
+    ok = {bb.BDS_TILE_W16: True, bb.BDS_TILE_W32: np_ % 32 == 0, bb.BDS_TILE_G64: np_ % 64 == 0,
+          bb.BDS_TILE_G128: np_ % 128 == 0}
+    return [c for c in codes if ok[c] and (not solve or c <= bb.BDS_TILE_W32)]
+
+
+def combos(n):
+    return list(itertools.product(fitting(n, False), fitting(n, False), fitting(n, True)))
+
+
+CASES = [(c, n) for n in (16, 40, 64, 128) for c in combos(n)]
+
+
+@pytest.mark.parametrize("tl,n", CASES, ids=[f"n{n}-{'.'.join(map(str, c))}" for c, n in CASES])
+def test_every_tile_choice_matches_oracle(S, tl, n):
+    _say("tiles", n, tl)
+    N, d = 37, 3
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=n + 7)
+    F = S.factor(dev(Ad), dev(As), tiles=bb.tiles(*tl))
+    X = F.solve(dev(B)).cpu().numpy()
+    assert F.info()["status"] == 0
+    assert relerr(X, oracle.solve(Ad, As, B)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("tl", [(bb.BDS_TILE_G64, bb.BDS_TILE_G128, bb.BDS_TILE_W16),
+                                (bb.BDS_TILE_W32, bb.BDS_TILE_G64, bb.BDS_TILE_W32),
+                                (bb.BDS_TILE_G128, bb.BDS_TILE_W16, bb.BDS_TILE_W32)])
+def test_mixed_precision_tile_choices_refine_to_oracle(S, prec, tl):
+    _say("mixed tiles", prec, tl)
+    Ad, As, _, B = inputs.gen_dd(45, 128, 2, seed=3)
+    F = S.factor(dev(Ad), dev(As), prec=prec, tiles=bb.tiles(*tl))
+    X = F.solve(dev(B)).cpu().numpy()
+    assert F.info()["converged"] == 1
+    assert relerr(X, oracle.solve(Ad, As, B)) <= 1e-12
+
+
+def test_changing_tiles_on_the_same_buffers_is_not_stale(S):
+    """Factor/solve graphs are cached per argument set; the tile field is part of the key."""
+    _say("tiles graph key")
+    Ad, As, _, B = inputs.gen_dd(50, 64, 2, seed=5)
+    Ad_t, As_t, B_t = dev(Ad), dev(As), dev(B)
+    F = S.factor(Ad_t, As_t, tiles=bb.tiles(bb.BDS_TILE_G64, bb.BDS_TILE_G64, bb.BDS_TILE_W32))
+    X1 = F.solve(B_t).clone()
+    F.tiles = bb.tiles(bb.BDS_TILE_W16, bb.BDS_TILE_W32, bb.BDS_TILE_W16)
+    F.refactor(check=True)
+    X2 = F.solve(B_t)
+    ref = oracle.solve(Ad, As, B)
+    assert relerr(X1.cpu().numpy(), ref) <= 1e-12 and relerr(X2.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("N,n,d,prec", [(200, 32, 2, "f64"), (64, 16, 1, "f64"), (300, 128, 4, "f64"),
+                                         (120, 64, 1, "f32")])
+def test_tune_picks_a_valid_configuration(S, N, n, d, prec):
+    _say("tune", N, n, d, prec)
+    Ad, As, _, B = inputs.gen_dd(N, n, d, seed=N)
+    B_t = dev(B)
+    F = S.factor(dev(Ad), dev(As), prec=prec)
+    choice = F.tune(B_t, reps=2)
+    assert choice["nstar"] >= 1 and choice["nstar"] <= max(64, 1)
+    assert all(choice[k] != "rule" for k in ("couple", "schur", "solve"))
+    X = F.solve(B_t).cpu().numpy()
+    assert relerr(X, oracle.solve(Ad, As, B)) <= 1e-12
+    # the tuned factor keeps working for another right-hand side
+    B2 = np.random.default_rng(1).standard_normal(B.shape)
+    assert relerr(F.solve(dev(B2)).cpu().numpy(), oracle.solve(Ad, As, B2)) <= 1e-12
+
+
+def test_tune_keeps_fields_the_caller_fixed(S):
+    _say("tune fixed fields")
+    Ad, As, _, B = inputs.gen_dd(80, 64, 2, seed=9)
+    fixed = bb.tiles(couple=bb.BDS_TILE_W16)
+    F = S.factor(dev(Ad), dev(As), nstar=4, tiles=fixed)
+    choice = F.tune(dev(B), reps=1)
+    assert choice["nstar"] == 4 and choice["couple"] == "w16"
+
+
+def test_tune_batched_matches_oracle(S):
+    _say("tune batched")
+    specs = [(40, 16, 1), (70, 32, 4), (33, 64, 1), (9, 8, 2), (128, 64, 4), (50, 32, 1)]
+    systems = [inputs.gen_dd(N, n, d, seed=11 + k) for k, (N, n, d) in enumerate(specs)]
+    Ads = [dev(s[0]) for s in systems]
+    Ass = [dev(s[1]) for s in systems]
+    Bs = [dev(s[3]) for s in systems]
+    F = S.factor_batched(Ads, Ass)
+    choice = F.tune(Bs, reps=1)
+    assert set(choice) == {16, 32, 64}
+    Xs = F.solve(Bs)
+    for (Ad, As, _, B), X in zip(systems, Xs):
+        assert relerr(X.cpu().numpy(), oracle.solve(Ad, As, B)) <= 1e-12
