@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--nstar", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (library rule for nstar and tile shapes)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -285,6 +287,10 @@ def main():
         F.solve(Bs, outs=Xs, refine_tol=tol)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t_init
+        t_tune = time.perf_counter()
+        tuning = None if args.no_tune else {str(k): v for k, v in F.tune(Bs, refine_tol=tol).items()}
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t_tune
 
         def step():
             F.refactor()
@@ -316,6 +322,11 @@ def main():
             F.backward(X_t, Wt)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t_init
+        t_tune = time.perf_counter()
+        tuning = None if args.no_tune else F.tune(B_t, refine_tol=tol)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t_tune
+        nstar_eff = F.nstar if F.nstar > 0 else nstar_eff
 
         def step():
             F.refactor()
@@ -335,8 +346,8 @@ def main():
         config = {"workload": args.workload, "N": N, "n": n, "d": d, "prec": prec, "generator": kind,
                   **({"kappa": w["kappa"]} if "kappa" in w else {}), "nstar": nstar_eff,
                   **({"adjoint": True} if adjoint else {})}
-    print(f"[bench] workload {args.workload} ({prec}): inputs {t_gen:.1f} s, init {t_init:.2f} s",
-          file=sys.stderr, flush=True)
+    print(f"[bench] workload {args.workload} ({prec}): inputs {t_gen:.1f} s, init {t_init:.2f} s, "
+          f"tune {t_tune:.2f} s -> {tuning}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()
@@ -421,6 +432,8 @@ def main():
         "refine_iters": iters,
         "wall_s_timed": wall,
         "init_s": t_init,
+        "tune_s": t_tune,
+        "tuning": tuning,
         "roofline": roof,
         "kernels": kernels,
         "ms_per_step_kernel_by_kernel": ms_step_traced,
