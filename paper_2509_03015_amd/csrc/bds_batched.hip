@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/bds.h"
+#include "bds_graph.hpp"
 #include "bds_host.hpp"
 #include "bds_kernels.hpp"
 #include "bds_plan.hpp"
@@ -177,7 +178,6 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
 {
     using T = typename Stor<C>::type;
     const int K = (int)bp.K;
-    BDS_TRY(launch_clear_info(info, K, st));
     Table tab(fws, bp.ftab, bp.ftab_bytes);
     // packing of systems whose n is not a multiple of 16
     std::vector<PackRec> packs;
@@ -290,24 +290,47 @@ int factor_batched_impl(const BatchPlan& bp, const double* const* Ad, const doub
         std::copy(c1.begin(), c1.end(), h);
     }
     BDS_TRY(tab.upload(st));
-
-    BDS_TRY(launch_pack_tab(pack_dev, pack_start, (int)packs.size(), pack_tot, st));
-    // levels in order; the groups of one level are independent of each other
-    for (const LevelTab& L : lt) {
-        if (L.level == 0) {
-            BDS_TRY(launch_factor_level<C, double>(FacLv<T, double>{}, static_cast<const FacLv<T, double>*>(L.recs),
-                                                   L.sd, L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np, L.tl, st));
-        } else {
-            BDS_TRY(launch_factor_level<C, T>(FacLv<T, T>{}, static_cast<const FacLv<T, T>*>(L.recs), L.sd, L.sc,
-                                              L.ss, L.cnt, L.td, L.tc, L.ts, L.np, L.tl, st));
-        }
-    }
     int np0 = 16, np1 = 16;
     for (const auto& c : c0) np0 = std::max(np0, c.np);
     for (const auto& c : c1) np1 = std::max(np1, c.np);
-    BDS_TRY(launch_coarse_factor<double>(CoarseFac<double>{}, c0_dev, (int)c0.size(), np0, st));
-    BDS_TRY(launch_coarse_factor<T>(CoarseFac<T>{}, c1_dev, (int)c1.size(), np1, st));
-    return BDS_OK;
+
+    // The launch sequence reads every per-system argument from the tables just
+    // uploaded, so it depends only on the table addresses and the unit counts:
+    // it is recorded once per such signature and replayed as a graph.
+    std::vector<int64_t> sig = {(int64_t)(uintptr_t)pack_dev, (int64_t)(uintptr_t)pack_start,
+                                (int64_t)packs.size(), pack_tot, (int64_t)(uintptr_t)c0_dev, (int64_t)c0.size(), np0,
+                                (int64_t)(uintptr_t)c1_dev, (int64_t)c1.size(), np1};
+    for (const LevelTab& L : lt) {
+        const int64_t v[] = {L.level, L.np, L.tl.couple, L.tl.schur, L.tl.sol, (int64_t)(uintptr_t)L.recs,
+                             (int64_t)(uintptr_t)L.sd, (int64_t)(uintptr_t)L.sc, (int64_t)(uintptr_t)L.ss, L.cnt,
+                             L.td, L.tc, L.ts};
+        sig.insert(sig.end(), v, v + sizeof(v) / sizeof(v[0]));
+    }
+    GraphKey key;
+    key.kind = 3;
+    key.count = K;
+    key.add((uint64_t)PrecOf<C>::value);
+    key.add(fws);
+    key.add(info);
+    key.digest = hash_bytes(0, sig.data(), sig.size() * sizeof(int64_t));
+    return run_graph(key, st, [&](hipStream_t s) -> int {
+        BDS_TRY(launch_clear_info(info, K, s));
+        BDS_TRY(launch_pack_tab(pack_dev, pack_start, (int)packs.size(), pack_tot, s));
+        // levels in order; the groups of one level are independent of each other
+        for (const LevelTab& L : lt) {
+            if (L.level == 0) {
+                BDS_TRY(launch_factor_level<C, double>(FacLv<T, double>{},
+                                                       static_cast<const FacLv<T, double>*>(L.recs), L.sd, L.sc,
+                                                       L.ss, L.cnt, L.td, L.tc, L.ts, L.np, L.tl, s));
+            } else {
+                BDS_TRY(launch_factor_level<C, T>(FacLv<T, T>{}, static_cast<const FacLv<T, T>*>(L.recs), L.sd,
+                                                  L.sc, L.ss, L.cnt, L.td, L.tc, L.ts, L.np, L.tl, s));
+            }
+        }
+        BDS_TRY(launch_coarse_factor<double>(CoarseFac<double>{}, c0_dev, (int)c0.size(), np0, s));
+        BDS_TRY(launch_coarse_factor<T>(CoarseFac<T>{}, c1_dev, (int)c1.size(), np1, s));
+        return BDS_OK;
+    });
 }
 
 // One solve through the stored hierarchies of the systems in `act`: B0[k] -> X0[k] (padded).

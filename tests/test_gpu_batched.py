@@ -132,3 +132,28 @@ def test_batched_512_uneven_systems(S, prec):
         Ad, As, _, B = systems[k]
         ref = oracle.solve(Ad, As, B) if prec == "f64" else oracle.solve_ld(Ad, As, B)
         assert relerr(Xs[k], ref) <= (1e-12 if prec == "f64" else 1e-10), (k, Ad.shape)
+
+
+def test_batched_factor_replay_reads_current_values(S):
+    """The batched factor's launch sequence is replayed as a graph; a refactor after the matrices changed
+    in place (same buffers) must use the new values, and the task tables of another batch in between
+    must not leak into the replay."""
+    _say("batched graph replay")
+    systems = uneven_systems(seed0=40)
+    Ads = [dev(s[0]) for s in systems]
+    Ass = [dev(s[1]) if s[0].shape[0] > 1 else None for s in systems]
+    Bs = [dev(s[3]) for s in systems]
+    F = S.factor_batched(Ads, Ass)
+    F.solve(Bs)
+    # another batch of different shapes factorised in between
+    other = uneven_systems(seed0=90)[:5]
+    S.factor_batched([dev(s[0]) for s in other], [dev(s[1]) if s[0].shape[0] > 1 else None for s in other])
+    for k, (Ad, As, _, _) in enumerate(systems):
+        Ads[k].copy_(dev(2.0 * Ad))
+        if Ass[k] is not None:
+            Ass[k].copy_(dev(2.0 * As))
+    for _ in range(2):
+        F.refactor(check=True)
+        Xs = F.solve(Bs)
+        for (Ad, As, _, B), X in zip(systems, Xs):
+            assert relerr(X.cpu().numpy(), oracle.solve(2.0 * Ad, 2.0 * As, B)) <= 1e-12, Ad.shape
