@@ -136,7 +136,7 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_03015_amd", "csrc", "bds_kernels.
 
 def source_digest() -> str:
     h = hashlib.sha256()
-    for name in ("bds_kernels.hip", "bds_device.hpp"):
+    for name in ("bds_kernels.hip", "bds_device.hpp", "bds_gemm.hpp", "bds_chol.hpp"):
         with open(os.path.join(ROOT, "paper_2509_03015_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

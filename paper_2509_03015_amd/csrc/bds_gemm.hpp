@@ -89,6 +89,9 @@ __device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[Chun
 // triangular (column n of the output needs k <= n only); SKIP_SYM, the output
 // tile is a diagonal tile of a symmetric matrix of which only the lower
 // triangle is kept (16 x 16 tiles strictly above the diagonal are left out).
+// With SKIP_SYM and sym set, every term is a Gram product (A and B are the
+// same view and m0 == n0), so the B operand is read from A's LDS buffer and
+// loaded only once.
 enum { SKIP_NONE = 0, SKIP_TRI_B = 1, SKIP_SYM = 2 };
 
 // Accumulator tiles (ta, tb), bit ta * R + tb, of wave (wm, wn) that take part.
@@ -126,6 +129,7 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
     constexpr int E = ChunkEpt<MT>::value;
     constexpr int LD = TileLd<V>::value;
     const int w = wave_id(), wm = w >> 1, wn = w & 1;
+    const bool gram = SKIP == SKIP_SYM && sym;
     const int l = lane_id(), i = l & 15, g = l >> 4;
 
     static_assert(NTERM == 1 || NTERM == 2, "one or two terms");
@@ -148,9 +152,9 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
         const View<TA> va = view_a(t);
         const View<TB> vb = view_b(t);
         chunk_load<V, MT>(va, m0, k, ra);
-        chunk_load<V, MT>(vb, n0, k, rb);
+        if (!gram) chunk_load<V, MT>(vb, n0, k, rb);
         chunk_store<MT>(va.kc, sm.a[0], ra);
-        chunk_store<MT>(vb.kc, sm.b[0], rb);
+        if (!gram) chunk_store<MT>(vb.kc, sm.b[0], rb);
     }
     __syncthreads();
     for (int c = 0; c < nch; ++c) {
@@ -163,10 +167,10 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
             kc_a = va.kc;
             kc_b = vb.kc;
             chunk_load<V, MT>(va, m0, k1, ra);
-            chunk_load<V, MT>(vb, n0, k1, rb);
+            if (!gram) chunk_load<V, MT>(vb, n0, k1, rb);
         }
         const V* As = sm.a[c & 1] + (16 * wm + i) * LD + 4 * g;
-        const V* Bs = sm.b[c & 1] + (16 * wn + i) * LD + 4 * g;
+        const V* Bs = (gram ? sm.a[c & 1] : sm.b[c & 1]) + (16 * wn + i) * LD + 4 * g;
         // MFMAs of this chunk for the accumulator tiles in MASK
         auto body = [&](auto mask_c) {
             constexpr unsigned MASK = decltype(mask_c)::value;
@@ -241,7 +245,7 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
         }
         if (c + 1 < nch) {
             chunk_store<MT>(kc_a, sm.a[(c + 1) & 1], ra);
-            chunk_store<MT>(kc_b, sm.b[(c + 1) & 1], rb);
+            if (!gram) chunk_store<MT>(kc_b, sm.b[(c + 1) & 1], rb);
         }
         __syncthreads();
     }
