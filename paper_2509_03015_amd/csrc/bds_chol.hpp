@@ -44,7 +44,7 @@ template <typename T, int NT> struct CholSmem {
     T pan[NT][16 * LD];  // column panel of L / row panel of X^T
     // pivot tiles, double-buffered by panel parity: the pivot of panel J + 1 is
     // factorised while panel J is still being used
-    T dg[2][16 * LD];    // pivot tile (symmetric), then its factor
+    T dg[2][16 * LD];    // pivot tile (symmetric)
     T di[2][16 * LD];    // D = inverse of the pivot's Cholesky factor, row-major
     T dt[2][16 * LD];    // D^T, row-major
     int bad;
@@ -171,46 +171,48 @@ __device__ __forceinline__ void pivot_chol_step(T (&a)[16], T& rv, int c, int& b
     }(std::make_integer_sequence<int, 15 - K>{});
 }
 
+// Step k of the forward substitution L X = I for column c of X (lane c of
+// each row of 16 lanes): x[k] /= L[k][k], then x[r] -= L[r][k] x[k] for
+// r > k.  Row r of L is held by lane r (a[] after the factorisation, rv its
+// reciprocal pivot), so its entries arrive by row broadcast.
+template <typename T, int K>
+__device__ __forceinline__ void pivot_inv_step(const T (&a)[16], T rv, T (&x)[16])
+{
+    pin(x[K]);
+    const T xk = x[K] * row_bcast<K>(rv);
+    x[K] = xk;
+    [&]<int... R>(std::integer_sequence<int, R...>) {
+        ((x[K + 1 + R] -= row_bcast<K + 1 + R>(a[K]) * xk), ...);
+    }(std::make_integer_sequence<int, 15 - K>{});
+}
+
 // Factorise the 16 x 16 symmetric pivot tile of panel J, staged in
 // sm.dg[J & 1], and invert the factor: sm.di[J & 1] = L^-1 and
 // sm.dt[J & 1] = (L^-1)^T (both row-major), by the calling wave.  The
-// factorisation keeps column c of the working matrix in
-// lane c of each row of 16 lanes (the four rows compute the same values) and
-// leaves row c of L there, which is written back over sm.dg with the
-// reciprocal of the pivot on the diagonal; the forward substitution L X = I
-// then gives lane c column c of X = L^-1, reading the entries of L by
-// broadcast from LDS.  Records the first non-positive pivot
-// (column 16 J + k) in sm.bad.
+// factorisation keeps column c of the working matrix in lane c of each row
+// of 16 lanes (the four rows compute the same values) and leaves row c of L
+// there; the forward substitution L X = I then gives lane c column c of
+// X = L^-1, taking the entries of L by row broadcast from the lanes that hold
+// them, all in registers.  Records the first non-positive pivot (column
+// 16 J + k) in sm.bad.
 template <typename T, int NT>
 __device__ __forceinline__ void pivot_factor(CholSmem<T, NT>& sm, int J)
 {
     constexpr int LD = TileLd<T>::value;
     const int l = lane_id(), c = l & 15, b = J & 1;
-    T* dg = sm.dg[b];
-    {
-        T a[16], rv = (T)0;
+    const T* dg = sm.dg[b];
+    T a[16], rv = (T)0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) a[r] = dg[r * LD + c];
-        int bad = -1;
-        [&]<int... K>(std::integer_sequence<int, K...>) { (pivot_chol_step<T, K>(a, rv, c, bad), ...); }(
-            std::make_integer_sequence<int, 16>{});
-        // row c of L, with 1 / L[c][c] in place of its diagonal entry
-        if (l < 16) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) dg[c * LD + k] = (k == c) ? rv : a[k];
-        }
-        if (l == 0 && bad >= 0 && sm.bad < 0) sm.bad = 16 * J + bad;
-    }
-    wave_sync();
+    for (int r = 0; r < 16; ++r) a[r] = dg[r * LD + c];
+    int bad = -1;
+    [&]<int... K>(std::integer_sequence<int, K...>) { (pivot_chol_step<T, K>(a, rv, c, bad), ...); }(
+        std::make_integer_sequence<int, 16>{});
+    if (l == 0 && bad >= 0 && sm.bad < 0) sm.bad = 16 * J + bad;
     T x[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) x[r] = (r == c) ? (T)1 : (T)0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        x[k] *= dg[k * LD + k];
-#pragma unroll
-        for (int r = k + 1; r < 16; ++r) x[r] -= dg[r * LD + k] * x[k];
-    }
+    [&]<int... K>(std::integer_sequence<int, K...>) { (pivot_inv_step<T, K>(a, rv, x), ...); }(
+        std::make_integer_sequence<int, 16>{});
     if (l < 16) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
