@@ -93,7 +93,39 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
     using V = typename Stor<T>::type;
     const int l = lane_id();
     const int i = l & 15, g = l >> 4;
-    for (int kc = k0; kc < k1; kc += 16) {
+    int kc = k0;
+    // FP32 rows feeding FP64 products (solves with a low-precision factor): 32 k per
+    // step, so that each lane reads 32 contiguous bytes of A as an FP64 row does;
+    // lane group g takes k = 8g .. 8g+7 of the 32, for A and B alike
+    constexpr bool WIDE = std::is_same<T, double>::value && sizeof(SA) == 4 && A_MK;
+    if constexpr (WIDE) {
+        for (; kc + 32 <= k1; kc += 32) {
+            const int k = kc + 8 * g;
+            V a[RM][8], b[RN][8];
+#pragma unroll
+            for (int ta = 0; ta < RM; ++ta) {
+                const int m = m0 + 16 * ta + i;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) a[ta][s] = (V)A[(int64_t)m * lda + k + s];
+            }
+#pragma unroll
+            for (int tb = 0; tb < RN; ++tb) {
+                const int n = n0 + 16 * tb + i;
+                const bool ok = !B_MASK || n < ncols;
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    b[tb][s] = ok ? (B_NK ? (V)B[(int64_t)n * ldb + k + s] : (V)B[(int64_t)(k + s) * ldb + n])
+                                  : (V)0;
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+#pragma unroll
+                for (int ta = 0; ta < RM; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < RN; ++tb) acc[ta][tb] = mma(a[ta][s], b[tb][s], acc[ta][tb]);
+        }
+    }
+    for (; kc < k1; kc += 16) {
         const int k = kc + 4 * g;
         V a[RM][4], b[RN][4];
 #pragma unroll
