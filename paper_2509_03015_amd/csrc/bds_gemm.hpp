@@ -4,10 +4,11 @@
 // A work-group of 4 waves (2 x 2) accumulates an MT x MT output tile
 // C += sum over terms of op(A_t) op(B_t); each wave owns an (MT/2) x (MT/2)
 // sub-tile as (MT/32)^2 MFMA accumulator tiles.  The contraction index k runs
-// over the terms one after the other in chunks of 16: a chunk of both
-// operands (MT x 16 each) is loaded from global memory into registers while
-// the previous chunk is multiplied out of LDS, then stored into the other LDS
-// buffer (double buffering, one barrier per chunk).
+// over the terms one after the other in chunks of KC (16, or 32 for FP32 on
+// large blocks): a chunk of both operands (MT x KC each) is loaded from global
+// memory into registers while the previous chunk is multiplied out of LDS,
+// then stored into the other LDS buffer (double buffering, one barrier per
+// chunk).
 //
 // Operands are given as "rows x k" views: element (r, k) of a view is
 // p[r * ld + k] when kc (k contiguous) or p[k * ld + r] otherwise.  A is
@@ -32,54 +33,57 @@ template <typename T> struct View {
 template <typename TA, typename TB> struct Term {
     View<TA> a;
     View<TB> b;
-    int k0, k1;  // multiples of 16
+    int k0, k1;  // multiples of the chunk depth KC
 };
 
-template <typename T, int MT> struct GemmSmem {
-    static constexpr int LD = TileLd<T>::value;
+// Depth KC of one K chunk: 16, or 32 for FP32 products on large blocks (their
+// MFMAs take half the cycles per k step of FP64, so a deeper chunk keeps the
+// work per barrier and the bytes in flight per work-group as for FP64; the
+// launcher chooses).
+template <typename T, int MT, int KC> struct GemmSmem {
+    static constexpr int LD = KC + 16 / (int)sizeof(T);  // row stride: KC elements plus 16 bytes
     T a[2][MT * LD];
     T b[2][MT * LD];
 };
 
-// Elements per thread and operand of one chunk (MT x 16 by 256 threads).
-template <int MT> struct ChunkEpt { static constexpr int value = MT / 16; };
+// Elements per thread and operand of one chunk (MT x KC by 256 threads).
+template <int MT, int KC> struct ChunkEpt { static constexpr int value = MT * KC / 256; };
 
-// Global -> registers: the thread's share of rows [r0, r0 + MT) x k [k, k + 16).
-template <typename V, int MT, typename T>
-__device__ __forceinline__ void chunk_load(const View<T>& v, int r0, int k, V (&reg)[ChunkEpt<MT>::value])
+// Global -> registers: the thread's share of rows [r0, r0 + MT) x k [k, k + KC).
+template <typename V, int MT, int KC, typename T>
+__device__ __forceinline__ void chunk_load(const View<T>& v, int r0, int k, V (&reg)[ChunkEpt<MT, KC>::value])
 {
-    constexpr int E = ChunkEpt<MT>::value;
+    constexpr int E = ChunkEpt<MT, KC>::value;
     const int t = threadIdx.x;
     if (v.kc) {
-        // 16 / E threads per row, E consecutive k each
-        const int row = t / (16 / E), kk = (t % (16 / E)) * E;
+        // KC / E threads per row, E consecutive k each
+        const int row = t / (KC / E), kk = (t % (KC / E)) * E;
         const T* src = v.p + (int64_t)(r0 + row) * v.ld + k + kk;
 #pragma unroll
         for (int q = 0; q < E; ++q) reg[q] = (V)src[q];
     } else {
-        // 16 consecutive threads take the 16 k of one group of E consecutive rows
-        // (a 64-byte read each), so that their transposed LDS writes below fall
-        // in consecutive banks
-        const int kk = t & 15, row = (t >> 4) * E;
+        // KC consecutive threads take the KC k of one group of E consecutive rows,
+        // so that their transposed LDS writes below fall in consecutive banks
+        const int kk = t % KC, row = (t / KC) * E;
         const T* src = v.p + (int64_t)(k + kk) * v.ld + r0 + row;
 #pragma unroll
         for (int q = 0; q < E; ++q) reg[q] = (V)src[q];
     }
 }
 
-// Registers -> LDS (rows x 16, row stride LD), matching chunk_load's split.
-template <int MT, typename V>
-__device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[ChunkEpt<MT>::value])
+// Registers -> LDS (rows x KC, row stride LD), matching chunk_load's split.
+template <int MT, int KC, typename V>
+__device__ __forceinline__ void chunk_store(bool kc, V* dst, const V (&reg)[ChunkEpt<MT, KC>::value])
 {
-    constexpr int E = ChunkEpt<MT>::value;
-    constexpr int LD = TileLd<V>::value;
+    constexpr int E = ChunkEpt<MT, KC>::value;
+    constexpr int LD = GemmSmem<V, MT, KC>::LD;
     const int t = threadIdx.x;
     if (kc) {
-        const int row = t / (16 / E), kk = (t % (16 / E)) * E;
+        const int row = t / (KC / E), kk = (t % (KC / E)) * E;
 #pragma unroll
         for (int q = 0; q < E; ++q) dst[row * LD + kk + q] = reg[q];
     } else {
-        const int kk = t & 15, row = (t >> 4) * E;
+        const int kk = t % KC, row = (t / KC) * E;
 #pragma unroll
         for (int q = 0; q < E; ++q) dst[(row + q) * LD + kk] = reg[q];
     }
@@ -119,26 +123,27 @@ template <int R> constexpr unsigned mask_lower(int w)
 // with work left) or once per tile (SKIP_SYM, when sym is set: the wave's
 // tiles on or below the diagonal); a branch per MFMA would break the
 // accumulator chains apart.
-template <typename C, int MT, int NTERM, int SKIP = SKIP_NONE, typename TA, typename TB>
+template <typename C, int MT, int KC, int NTERM, int SKIP = SKIP_NONE, typename TA, typename TB>
 __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT / 32][MT / 32],
                                                 const Term<TA, TB> (&terms)[NTERM], int m0, int n0,
-                                                GemmSmem<typename Stor<C>::type, MT>& sm, bool sym = false)
+                                                GemmSmem<typename Stor<C>::type, MT, KC>& sm, bool sym = false)
 {
     using V = typename Stor<C>::type;
     constexpr int R = MT / 32;
-    constexpr int E = ChunkEpt<MT>::value;
-    constexpr int LD = TileLd<V>::value;
+    constexpr int E = ChunkEpt<MT, KC>::value;
+    constexpr int LD = GemmSmem<V, MT, KC>::LD;
+    static_assert(KC == 16 || KC == 32, "chunk depth 16 or 32");
     const int w = wave_id(), wm = w >> 1, wn = w & 1;
     const bool gram = SKIP == SKIP_SYM && sym;
     const int l = lane_id(), i = l & 15, g = l >> 4;
 
     static_assert(NTERM == 1 || NTERM == 2, "one or two terms");
     // chunk c -> (term, k): the chunks of term 0, then those of term 1
-    const int nch0 = (terms[0].k1 - terms[0].k0) / 16;
-    const int nch = nch0 + (NTERM == 2 ? (terms[NTERM - 1].k1 - terms[NTERM - 1].k0) / 16 : 0);
+    const int nch0 = (terms[0].k1 - terms[0].k0) / KC;
+    const int nch = nch0 + (NTERM == 2 ? (terms[NTERM - 1].k1 - terms[NTERM - 1].k0) / KC : 0);
     auto locate = [&](int c, int& t, int& k) {
         t = (NTERM == 2 && c >= nch0) ? 1 : 0;
-        k = t == 0 ? terms[0].k0 + 16 * c : terms[NTERM - 1].k0 + 16 * (c - nch0);
+        k = t == 0 ? terms[0].k0 + KC * c : terms[NTERM - 1].k0 + KC * (c - nch0);
     };
     // the term's views, chosen with selects (indexing the array with a run-time
     // index would put it in scratch memory)
@@ -151,10 +156,10 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
         locate(0, t, k);
         const View<TA> va = view_a(t);
         const View<TB> vb = view_b(t);
-        chunk_load<V, MT>(va, m0, k, ra);
-        if (!gram) chunk_load<V, MT>(vb, n0, k, rb);
-        chunk_store<MT>(va.kc, sm.a[0], ra);
-        if (!gram) chunk_store<MT>(vb.kc, sm.b[0], rb);
+        chunk_load<V, MT, KC>(va, m0, k, ra);
+        if (!gram) chunk_load<V, MT, KC>(vb, n0, k, rb);
+        chunk_store<MT, KC>(va.kc, sm.a[0], ra);
+        if (!gram) chunk_store<MT, KC>(vb.kc, sm.b[0], rb);
     }
     __syncthreads();
     for (int c = 0; c < nch; ++c) {
@@ -166,13 +171,13 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
             const View<TB> vb = view_b(t1);
             kc_a = va.kc;
             kc_b = vb.kc;
-            chunk_load<V, MT>(va, m0, k1, ra);
-            if (!gram) chunk_load<V, MT>(vb, n0, k1, rb);
+            chunk_load<V, MT, KC>(va, m0, k1, ra);
+            if (!gram) chunk_load<V, MT, KC>(vb, n0, k1, rb);
         }
         const V* As = sm.a[c & 1] + (16 * wm + i) * LD + 4 * g;
         const V* Bs = (gram ? sm.a[c & 1] : sm.b[c & 1]) + (16 * wn + i) * LD + 4 * g;
-        // MFMAs of this chunk for the accumulator tiles in MASK
-        auto body = [&](auto mask_c) {
+        // MFMAs of 16 k of this chunk (from koff) for the accumulator tiles in MASK
+        auto body = [&](auto mask_c, int koff) {
             constexpr unsigned MASK = decltype(mask_c)::value;
             auto on = [](int ta, int tb) { return ((MASK >> (ta * R + tb)) & 1u) != 0; };
             auto col_on = [&](int tb) {
@@ -183,10 +188,10 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
             if constexpr (std::is_same<C, bf16x>::value) {
                 V a[R][4], b[R][4];
 #pragma unroll
-                for (int ta = 0; ta < R; ++ta) ld4(As + 32 * ta * LD, a[ta]);
+                for (int ta = 0; ta < R; ++ta) ld4(As + koff + 32 * ta * LD, a[ta]);
 #pragma unroll
                 for (int tb = 0; tb < R; ++tb)
-                    if (col_on(tb)) ld4(Bs + 32 * tb * LD, b[tb]);
+                    if (col_on(tb)) ld4(Bs + koff + 32 * tb * LD, b[tb]);
 #pragma unroll
                 for (int ta = 0; ta < R; ++ta)
 #pragma unroll
@@ -200,12 +205,12 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
 #pragma unroll
                     for (int ta = 0; ta < R; ++ta)
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) a[ta][q] = As[32 * ta * LD + 2 * h + q];
+                        for (int q = 0; q < 2; ++q) a[ta][q] = As[koff + 32 * ta * LD + 2 * h + q];
 #pragma unroll
                     for (int tb = 0; tb < R; ++tb)
                         if (col_on(tb))
 #pragma unroll
-                            for (int q = 0; q < 2; ++q) b[tb][q] = Bs[32 * tb * LD + 2 * h + q];
+                            for (int q = 0; q < 2; ++q) b[tb][q] = Bs[koff + 32 * tb * LD + 2 * h + q];
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -219,33 +224,36 @@ __device__ __forceinline__ void wg_tile_product(typename AccT<C>::type (&acc)[MT
         using std::integral_constant;
         constexpr unsigned ALL = mask_cols_from<R>(0);
         static_assert(R <= 4, "at most four tiles per wave and direction");
-        if constexpr (SKIP == SKIP_TRI_B) {
-            int tc, kc;
-            locate(c, tc, kc);
-            // column tile wn + 2 tb needs the chunks cr = (k - n0) / 16 <= wn + 2 tb
-            const int cr = (kc - n0) >> 4;
-            const int tb0 = (tc == 0 && cr > wn) ? (cr - wn + 1) >> 1 : 0;
-            switch (tb0) {
-            case 0: body(integral_constant<unsigned, ALL>{}); break;
-            case 1: body(integral_constant<unsigned, mask_cols_from<R>(1)>{}); break;
-            case 2: body(integral_constant<unsigned, mask_cols_from<R>(2)>{}); break;
-            case 3: body(integral_constant<unsigned, mask_cols_from<R>(3)>{}); break;
-            default: break;  // no column tile of this wave is reached yet
+        int tc = 0, kcur = 0;
+        locate(c, tc, kcur);
+#pragma unroll
+        for (int koff = 0; koff < KC; koff += 16) {
+            if constexpr (SKIP == SKIP_TRI_B) {
+                // column tile wn + 2 tb needs the 16-k steps cr = (k - n0) / 16 <= wn + 2 tb
+                const int cr = (kcur + koff - n0) >> 4;
+                const int tb0 = (tc == 0 && cr > wn) ? (cr - wn + 1) >> 1 : 0;
+                switch (tb0) {
+                case 0: body(integral_constant<unsigned, ALL>{}, koff); break;
+                case 1: body(integral_constant<unsigned, mask_cols_from<R>(1)>{}, koff); break;
+                case 2: body(integral_constant<unsigned, mask_cols_from<R>(2)>{}, koff); break;
+                case 3: body(integral_constant<unsigned, mask_cols_from<R>(3)>{}, koff); break;
+                default: break;  // no column tile of this wave is reached yet
+                }
+            } else if constexpr (SKIP == SKIP_SYM) {
+                switch (sym ? w : 4) {
+                case 0: body(integral_constant<unsigned, mask_lower<R>(0)>{}, koff); break;
+                case 1: body(integral_constant<unsigned, mask_lower<R>(1)>{}, koff); break;
+                case 2: body(integral_constant<unsigned, mask_lower<R>(2)>{}, koff); break;
+                case 3: body(integral_constant<unsigned, mask_lower<R>(3)>{}, koff); break;
+                default: body(integral_constant<unsigned, ALL>{}, koff); break;
+                }
+            } else {
+                body(integral_constant<unsigned, ALL>{}, koff);
             }
-        } else if constexpr (SKIP == SKIP_SYM) {
-            switch (sym ? w : 4) {
-            case 0: body(integral_constant<unsigned, mask_lower<R>(0)>{}); break;
-            case 1: body(integral_constant<unsigned, mask_lower<R>(1)>{}); break;
-            case 2: body(integral_constant<unsigned, mask_lower<R>(2)>{}); break;
-            case 3: body(integral_constant<unsigned, mask_lower<R>(3)>{}); break;
-            default: body(integral_constant<unsigned, ALL>{}); break;
-            }
-        } else {
-            body(integral_constant<unsigned, ALL>{});
         }
         if (c + 1 < nch) {
-            chunk_store<MT>(kc_a, sm.a[(c + 1) & 1], ra);
-            if (!gram) chunk_store<MT>(kc_b, sm.b[(c + 1) & 1], rb);
+            chunk_store<MT, KC>(kc_a, sm.a[(c + 1) & 1], ra);
+            if (!gram) chunk_store<MT, KC>(kc_b, sm.b[(c + 1) & 1], rb);
         }
         __syncthreads();
     }

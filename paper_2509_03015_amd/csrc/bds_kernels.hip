@@ -270,13 +270,13 @@ static int64_t units_fac_schur_wg(int M, int np, int MT)
     return (int64_t)((M + 1) / 2) * (tp * (tp + 1) / 2 + tp * tp);
 }
 
-template <typename C, typename In, int MT, typename Tab>
+template <typename C, typename In, int MT, int KC, typename Tab>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 64 ? 4 : 2))) void k_fac_couple_wg(Tab tab)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
     constexpr int R = MT / 32;
-    __shared__ GemmSmem<T, MT> sm;
+    __shared__ GemmSmem<T, MT, KC> sm;
     const int64_t u = xcd_local_index(blockIdx.x, gridDim.x);
     if (u >= tab.total) return;
     int64_t loc;
@@ -294,18 +294,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 64 ? 
     // Wt = A[i,i-1]^T Li^T, Pr = A[i+1,i] Li^T; Li^T is upper triangular, so k < n0 + MT
     const View<In> op = which == 0 ? View<In>{s.As + (i - 1) * nn, np, false} : View<In>{s.As + i * nn, np, true};
     const Term<In, T> terms[1] = {{op, {s.Li + e * nn, np, true}, 0, min(np, n0 + MT)}};
-    wg_tile_product<C, MT, 1, SKIP_TRI_B>(acc, terms, m0, n0, sm);
+    wg_tile_product<C, MT, KC, 1, SKIP_TRI_B>(acc, terms, m0, n0, sm);
     T* out = (which == 0 ? s.Wt : s.Pr) + e * nn;
     wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
 }
 
-template <typename C, typename In, int MT, typename Tab>
+template <typename C, typename In, int MT, int KC, typename Tab>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 64 ? 4 : 2))) void k_fac_schur_wg(Tab tab)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
     constexpr int R = MT / 32;
-    __shared__ GemmSmem<T, MT> sm;
+    __shared__ GemmSmem<T, MT, KC> sm;
     const int64_t u = xcd_local_index(blockIdx.x, gridDim.x);
     if (u >= tab.total) return;
     int64_t loc;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MT <= 64 ? 
     // reads its lower triangle): diagonal macro tiles skip their strictly upper
     // 16 x 16 tiles and store no element above the diagonal
     const bool sym = diag && m0 == n0;
-    wg_tile_product<C, MT, 2, SKIP_SYM>(acc, terms, m0, n0, sm, sym);
+    wg_tile_product<C, MT, KC, 2, SKIP_SYM>(acc, terms, m0, n0, sm, sym);
     if (diag) {
         const In* a = s.Ad + 2 * j * nn;
         T* out = s.Adn + j * nn;
@@ -871,10 +871,19 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
         });
     });
     if (e != hipSuccess) return e;
+    // chunk depth of the work-group products: 32 for FP32 products on blocks of 128
+    // and more (measured faster there; 16 is faster for 64-wide blocks and BF16)
+    const bool deep = std::is_same<C, float>::value && np >= 128;
     e = with_table(one, tab, sc, K, tc, [&](auto t) {
         switch (tl.couple) {
-        case BDS_TILE_G128: BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 128><<<(unsigned)tc, 256, 0, st>>>(t)); break;
-        case BDS_TILE_G64: BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64><<<(unsigned)tc, 256, 0, st>>>(t)); break;
+        case BDS_TILE_G128:
+            if (deep) BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 128, 32><<<(unsigned)tc, 256, 0, st>>>(t));
+            else BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 128, 16><<<(unsigned)tc, 256, 0, st>>>(t));
+            break;
+        case BDS_TILE_G64:
+            if (deep) BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64, 32><<<(unsigned)tc, 256, 0, st>>>(t));
+            else BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64, 16><<<(unsigned)tc, 256, 0, st>>>(t));
+            break;
         case BDS_TILE_W32: BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(t)); break;
         default: BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(t)); break;
         }
@@ -883,8 +892,14 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
     if (e != hipSuccess) return e;
     return with_table(one, tab, ss, K, ts, [&](auto t) {
         switch (tl.schur) {
-        case BDS_TILE_G128: BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 128><<<(unsigned)ts, 256, 0, st>>>(t)); break;
-        case BDS_TILE_G64: BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64><<<(unsigned)ts, 256, 0, st>>>(t)); break;
+        case BDS_TILE_G128:
+            if (deep) BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 128, 32><<<(unsigned)ts, 256, 0, st>>>(t));
+            else BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 128, 16><<<(unsigned)ts, 256, 0, st>>>(t));
+            break;
+        case BDS_TILE_G64:
+            if (deep) BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64, 32><<<(unsigned)ts, 256, 0, st>>>(t));
+            else BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64, 16><<<(unsigned)ts, 256, 0, st>>>(t));
+            break;
         case BDS_TILE_W32: BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(t)); break;
         default: BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(t)); break;
         }
