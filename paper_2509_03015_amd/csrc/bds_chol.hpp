@@ -222,17 +222,19 @@ __device__ __forceinline__ void pivot_factor(CholSmem<T, NT>& sm, int J)
     }
 }
 
-// Row panel J of the inverse (16 x np) to global memory, by all WB waves of
-// the work-group: wave w writes rows w, w + WB, ..., each lane two adjacent
-// columns.  X[J][K] for K < J comes from the transposed tiles in sm.pan,
-// X[J][J] from sm.di[J & 1], and the tiles right of the diagonal are zero.
+// Row panel J of the inverse (16 x np, row stride ldl) to global memory, by
+// all WB waves of the work-group: wave w writes rows w, w + WB, ..., each lane
+// two adjacent columns.  X[J][K] for K < J comes from the transposed tiles in
+// sm.pan, X[J][J] from sm.di[J & 1], and the tiles right of the diagonal are
+// zero.
 template <typename T, int NT, int WB>
-__device__ __forceinline__ void store_row_panel(const CholSmem<T, NT>& sm, T* Li, int np, int J, int w)
+__device__ __forceinline__ void store_row_panel(const CholSmem<T, NT>& sm, T* Li, int np, int64_t ldl, int J,
+                                                int w)
 {
     constexpr int LD = TileLd<T>::value;
     const int l = lane_id();
     for (int r = w; r < 16; r += WB) {
-        T* dst = Li + (int64_t)(16 * J + r) * np;
+        T* dst = Li + (int64_t)(16 * J + r) * ldl;
         for (int c0 = 2 * l; c0 < np; c0 += 128) {
             const int K = c0 >> 4, c = c0 & 15;
             T v0 = (T)0, v1 = (T)0;
@@ -265,13 +267,14 @@ __device__ __forceinline__ void tile_of(int t, int& I, int& K)
 // one panel ahead: the owner of tile (J+1, J+1) updates it first in step 4 of
 // panel J, stages it and raises sm.ready, and the pivot wave factorises it
 // while the other waves finish panel J.
-//   A  (np x np, element type In, row-major): only the lower triangle is read;
-//   Li (np x np, storage of C, row-major): receives L^-1 (lower triangular,
-//      explicit zeros above the diagonal).
+//   A  (np x np, element type In, row-major, row stride lda): only the lower
+//      triangle is read;
+//   Li (np x np, storage of C, row-major, row stride ldl): receives L^-1
+//      (lower triangular, explicit zeros above the diagonal).
 // Returns the first column whose pivot is not positive (or NaN), else -1.
 template <typename C, int NT, int W, typename In>
-__device__ __forceinline__ int chol_inv_block(const In* A, typename Stor<C>::type* Li, int np,
-                                              CholSmem<typename Stor<C>::type, NT>& sm)
+__device__ __forceinline__ int chol_inv_block(const In* A, typename Stor<C>::type* Li, int np, int64_t lda,
+                                              int64_t ldl, CholSmem<typename Stor<C>::type, NT>& sm)
 {
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
@@ -294,7 +297,7 @@ __device__ __forceinline__ int chol_inv_block(const In* A, typename Stor<C>::typ
         for (int J = 0; J < nt; ++J) {
             __syncthreads();  // 1: panels published
             __syncthreads();  // 3: column J of L and row J of the inverse staged
-            store_row_panel<T, NT, W + 1>(sm, Li, np, J, w);
+            store_row_panel<T, NT, W + 1>(sm, Li, np, ldl, J, w);
             if (J + 1 < nt) {
                 // wait for the owner of tile (J+1, J+1) to stage it (it does so
                 // first thing in step 4, so the wait ends)
@@ -324,7 +327,7 @@ __device__ __forceinline__ int chol_inv_block(const In* A, typename Stor<C>::typ
             for (int r = 0; r < 4; ++r) {
                 const int row = acc_row<C>(g, r);
                 const int gr = 16 * I + row, gc = 16 * K + i;
-                acc[s][r] = (T)((I == K && i > row) ? A[(int64_t)gc * np + gr] : A[(int64_t)gr * np + gc]);
+                acc[s][r] = (T)((I == K && i > row) ? A[(int64_t)gc * lda + gr] : A[(int64_t)gr * lda + gc]);
             }
             if (I == 0 && K == 0) tile_stage<C, LD>(acc[s], sm.dg[0], false);
         }
@@ -379,7 +382,7 @@ __device__ __forceinline__ int chol_inv_block(const In* A, typename Stor<C>::typ
                 if (l == 0) __hip_atomic_store(&sm.ready, J + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
-        store_row_panel<T, NT, W + 1>(sm, Li, np, J, w);
+        store_row_panel<T, NT, W + 1>(sm, Li, np, ldl, J, w);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int t = w + s * W;

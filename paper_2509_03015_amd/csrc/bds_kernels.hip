@@ -165,9 +165,109 @@ __attribute__((amdgpu_waves_per_eu(NT <= 8 ? 2 : 1))) void k_fac_diag(Tab tab)
     const int np = s.np;
     const int64_t nn = (int64_t)np * np;
     const int64_t i = 2 * e + 1;
-    const int bad = chol_inv_block<C, NT, CholWaves<NT>::value, In>(s.Ad + i * nn, s.Li + e * nn, np, sm);
+    const int bad = chol_inv_block<C, NT, CholWaves<NT>::value, In>(s.Ad + i * nn, s.Li + e * nn, np, np, np, sm);
     if (bad >= 0 && threadIdx.x == 0)
         report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad);
+}
+
+// Blocks of 256 rows: the factor and inverse of A_ii by a 2 x 2 block
+// recursion over 128-row halves, so that the serial pivot chains run in the
+// 128-row kernel (several work-groups per CU) instead of one 16-wave
+// work-group per CU:
+//   L11^-1 = chol(A11)^-1               (k_fac_diag_half, first)
+//   L21 = A21 L11^-T                    (k_fac_diag_link, step 0)
+//   S = A22 - L21 L21^T                 (step 1)
+//   L22^-1 = chol(S)^-1                 (k_fac_diag_half, second)
+//   T = L21 L11^-1                      (step 2)
+//   X21 = -L22^-1 T                     (step 3)
+// so that Li = [L11^-1 0; X21 L22^-1].  L21 is kept in Li's lower-left
+// quadrant until X21 replaces it; S and then T live in the upper-right
+// quadrant, which step 3 clears at the end.  One work-group per interior in
+// every launch, so each launch takes the level's interior table unchanged.
+constexpr int kHalf = 128;
+
+template <typename C, typename In, bool SECOND, typename Tab>
+__global__ __launch_bounds__(chol_threads<8>())
+__attribute__((amdgpu_waves_per_eu(2))) void k_fac_diag_half(Tab tab)
+{
+    using T = typename Stor<C>::type;
+    __shared__ CholSmem<T, 8> sm;
+    const int64_t u = blockIdx.x;
+    if (u >= tab.total) return;
+    int64_t e;
+    const auto& s = tab.get(u, e);
+    const int np = s.np;
+    const int64_t nn = (int64_t)np * np;
+    const int64_t i = 2 * e + 1;
+    T* Li = s.Li + e * nn;
+    int bad;
+    if constexpr (!SECOND)
+        bad = chol_inv_block<C, 8, CholWaves<8>::value, In>(s.Ad + i * nn, Li, kHalf, np, np, sm);
+    else
+        bad = chol_inv_block<C, 8, CholWaves<8>::value, T>(Li + kHalf, Li + (int64_t)kHalf * np + kHalf, kHalf, np,
+                                                            np, sm);
+    if (bad >= 0 && threadIdx.x == 0)
+        report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad + (SECOND ? kHalf : 0));
+}
+
+template <typename C, typename In, int STEP, typename Tab>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fac_diag_link(Tab tab)
+{
+    using T = typename Stor<C>::type;
+    using Acc = typename AccT<C>::type;
+    constexpr int MT = 64, KC = 16, R = MT / 32, H = kHalf, TP = H / MT;
+    __shared__ GemmSmem<T, MT, KC> sm;
+    const int64_t u = blockIdx.x;
+    if (u >= tab.total) return;
+    int64_t e;
+    const auto& s = tab.get(u, e);
+    const int np = s.np;
+    const int64_t nn = (int64_t)np * np;
+    const int64_t i = 2 * e + 1;
+    const In* A = s.Ad + i * nn;
+    T* Li = s.Li + e * nn;
+    T* L11i = Li;                          // L11^-1
+    T* Low = Li + (int64_t)H * np;         // L21, then X21
+    T* Scr = Li + H;                       // S, then T
+    T* L22i = Li + (int64_t)H * np + H;    // L22^-1
+    for (int t = 0; t < TP * TP; ++t) {
+        const int tm = t / TP, tn = t % TP;
+        if (STEP == 1 && tn > tm) continue;  // S: lower macro tiles
+        const int m0 = MT * tm, n0 = MT * tn;
+        Acc acc[R][R];
+        acc_zero<C, R, R>(acc);
+        if constexpr (STEP == 0) {
+            // L21 = A21 L11^-T; L11^-T is upper triangular, so k < n0 + MT
+            const Term<In, T> terms[1] = {{{A + (int64_t)H * np, np, true}, {L11i, np, true}, 0, min(H, n0 + MT)}};
+            wg_tile_product<C, MT, KC, 1, SKIP_TRI_B>(acc, terms, m0, n0, sm);
+            wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { Low[(int64_t)m * np + n] = v; });
+        } else if constexpr (STEP == 1) {
+            // S = A22 - L21 L21^T, lower triangle
+            const bool sym = tm == tn;
+            const Term<T, T> terms[1] = {{{Low, np, true}, {Low, np, true}, 0, H}};
+            wg_tile_product<C, MT, KC, 1, SKIP_SYM>(acc, terms, m0, n0, sm, sym);
+            const In* a22 = A + (int64_t)H * np + H;
+            wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) {
+                if (!sym || n <= m) Scr[(int64_t)m * np + n] = (T)a22[(int64_t)m * np + n] - v;
+            });
+        } else if constexpr (STEP == 2) {
+            // T = L21 L11^-1; L11^-1 is lower triangular, so k >= n0
+            const Term<T, T> terms[1] = {{{Low, np, true}, {L11i, np, false}, n0, H}};
+            wg_tile_product<C, MT, KC, 1>(acc, terms, m0, n0, sm);
+            wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { Scr[(int64_t)m * np + n] = v; });
+        } else {
+            // X21 = -L22^-1 T; L22^-1 is lower triangular, so k < m0 + MT
+            const Term<T, T> terms[1] = {{{L22i, np, true}, {Scr, np, false}, 0, min(H, m0 + MT)}};
+            wg_tile_product<C, MT, KC, 1>(acc, terms, m0, n0, sm);
+            wg_tile_foreach<C, MT>(acc, m0, n0, [&](int m, int n, T v) { Low[(int64_t)m * np + n] = -v; });
+        }
+        __syncthreads();  // the LDS buffers are reused by the next tile
+    }
+    if constexpr (STEP == 3) {
+        // every read of the scratch quadrant of this interior is done: clear it
+        for (int q = threadIdx.x; q < H * H; q += blockDim.x)
+            Scr[(int64_t)(q / H) * np + q % H] = (T)0;
+    }
 }
 
 template <typename C, typename In, int R, typename Tab>
@@ -391,7 +491,7 @@ __global__ __launch_bounds__(chol_threads<NT>()) void k_coarse_factor(Tab tab)
         }
         __syncthreads();
         double* Lci = s.Lc + (int64_t)i * nn;
-        const int bad = chol_inv_block<double, NT, W, double>(s.Cw, Lci, np, sm);
+        const int bad = chol_inv_block<double, NT, W, double>(s.Cw, Lci, np, np, np, sm);
         if (bad >= 0 && threadIdx.x == 0)
             report_notspd(s.info, s.level, i, i << s.level, bad);
         if (i + 1 < s.Mc) {
@@ -864,6 +964,17 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                int64_t ts, int np, const Tiling& tl, hipStream_t st)
 {
     hipError_t e = with_table(one, tab, sd, K, td, [&](auto t) {
+        if (np == 2 * kHalf) {
+            // 2 x 2 recursion over 128-row halves (see k_fac_diag_half)
+            const unsigned nb = (unsigned)td, ct = chol_threads<8>();
+            BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false><<<nb, ct, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 0><<<nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 1><<<nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, true><<<nb, ct, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 2><<<nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 3><<<nb, 256, 0, st>>>(t));
+            return hipGetLastError();
+        }
         return dispatch_nt(np, [&](auto nt) {
             constexpr int NT = decltype(nt)::value;
             BDS_TIMED("fac_diag", st, k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(t));

@@ -124,6 +124,28 @@ def test_not_spd_is_reported(S, N, bad):
         oracle.factor(Ad, As)
 
 
+@pytest.mark.parametrize("half,col", [(0, 5), (1, 131), (1, 255)])
+def test_not_spd_in_either_half_of_a_256_block(S, half, col):
+    """Blocks of 256 rows are factorised as two 128-row halves; a non-positive pivot in either half is
+    reported, with its column counted from the start of the block."""
+    _say("not spd 256", half, col)
+    N, n = 9, 256
+    Ad, As, _, _ = inputs.gen_dd(N, n, 1, seed=21)
+    Ad = Ad.copy()
+    # make the leading (col + 1) x (col + 1) block of an interior singular at column col: a Schur pivot of zero
+    blk = 3                                   # an interior at level 0 (odd position)
+    v = np.linalg.cholesky(Ad[blk][:col, :col]) if col > 0 else None
+    row = Ad[blk][col, :col]
+    y = np.linalg.solve(v, row) if col > 0 else np.zeros(0)
+    Ad[blk][col, col] = float(y @ y) - 1.0    # pivot col becomes -1
+    F = S.factor(dev(Ad), dev(As), check=False)
+    inf = F.info()
+    assert inf["status"] == S.bb.BDS_ENOTSPD, inf
+    assert (inf["level"], inf["orig_block"], inf["column"]) == (0, blk, col), inf
+    with pytest.raises(oracle.OracleError):
+        oracle.factor(Ad, As)
+
+
 def test_nan_input_is_reported(S):
     _say("nan")
     Ad, As, _, _ = inputs.gen_dd(20, 16, 1, seed=9)
