@@ -170,7 +170,7 @@ __attribute__((amdgpu_waves_per_eu(NT <= 8 ? 2 : 1))) void k_fac_diag(Tab tab)
         report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad);
 }
 
-// Blocks of 256 rows: the factor and inverse of A_ii by a 2 x 2 block
+// FP64 blocks of 256 rows: the factor and inverse of A_ii by a 2 x 2 block
 // recursion over 128-row halves, so that the serial pivot chains run in the
 // 128-row kernel (several work-groups per CU) instead of one 16-wave
 // work-group per CU:
@@ -964,8 +964,10 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
                                int64_t ts, int np, const Tiling& tl, hipStream_t st)
 {
     hipError_t e = with_table(one, tab, sd, K, td, [&](auto t) {
-        if (np == 2 * kHalf) {
-            // 2 x 2 recursion over 128-row halves (see k_fac_diag_half)
+        if (std::is_same<C, double>::value && np == 2 * kHalf) {
+            // 2 x 2 recursion over 128-row halves (see k_fac_diag_half); FP64 only:
+            // in FP32 the explicit 128-row inverses cost the refinement an
+            // iteration at kappa ~ 1e6, which the 16-row pivot inverses do not
             const unsigned nb = (unsigned)td, ct = chol_threads<8>();
             BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false><<<nb, ct, 0, st>>>(t));
             BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 0><<<nb, 256, 0, st>>>(t));
