@@ -61,16 +61,15 @@ template <int NT> struct CholWaves { static constexpr int value = NT <= 2 ? 1 : 
 template <int NT> constexpr int chol_threads() { return 64 * (CholWaves<NT>::value + 1); }
 
 // Value of lane R of each 16-lane row, broadcast to the whole row (DPP
-// row_newbcast), kept in vector registers.
+// row_newbcast), kept in vector registers.  A double moves in one 64-bit DPP
+// move (v_mov_b64 with row_newbcast), not as two 32-bit halves.
 template <int R> __device__ __forceinline__ float row_bcast(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + R, 0xF, 0xF, true));
 }
 template <int R> __device__ __forceinline__ double row_bcast(double v)
 {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + R, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + R, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + R, 0xF, 0xF, true);
 }
 
 // Four consecutive elements starting at p (16-byte aligned for float, 32 for double).
@@ -174,15 +173,23 @@ __device__ __forceinline__ void pivot_chol_step(T (&a)[16], T& rv, int c, int& b
 // Step k of the forward substitution L X = I for column c of X (lane c of
 // each row of 16 lanes): x[k] /= L[k][k], then x[r] -= L[r][k] x[k] for
 // r > k.  Row r of L is held by lane r (a[] after the factorisation, rv its
-// reciprocal pivot), so its entries arrive by row broadcast.
+// reciprocal pivot), so its entries arrive by row broadcast.  The broadcasts
+// do not depend on x, so the compiler prepares them ahead of the chain; for
+// doubles the sources are pinned every second step, which bounds that
+// look-ahead to two steps (about 60 registers) instead of the whole sweep.
 template <typename T, int K>
 __device__ __forceinline__ void pivot_inv_step(const T (&a)[16], T rv, T (&x)[16])
 {
     pin(x[K]);
-    const T xk = x[K] * row_bcast<K>(rv);
+    T aK = a[K], rk = rv;
+    if constexpr (sizeof(T) == 8 && K % 2 == 0) {
+        pin(aK);
+        pin(rk);
+    }
+    const T xk = x[K] * row_bcast<K>(rk);
     x[K] = xk;
     [&]<int... R>(std::integer_sequence<int, R...>) {
-        ((x[K + 1 + R] -= row_bcast<K + 1 + R>(a[K]) * xk), ...);
+        ((x[K + 1 + R] -= row_bcast<K + 1 + R>(aK) * xk), ...);
     }(std::make_integer_sequence<int, 15 - K>{});
 }
 
