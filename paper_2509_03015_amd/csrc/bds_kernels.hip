@@ -22,6 +22,7 @@
 // Each separator receives its two contributions in a fixed order, so results
 // are deterministic (no atomics in the arithmetic).
 #include <algorithm>
+#include <atomic>
 
 #include "bds_chol.hpp"
 #include "bds_device.hpp"
@@ -151,10 +152,16 @@ int64_t units_resid(int N, int np, int d) { return (int64_t)N * (np / (16 * tile
 // ---------------------------------------------------------------------------
 // factorisation
 
-// Two work-groups per CU for blocks up to 128 (two waves per SIMD).
-template <typename C, typename In, int NT, typename Tab>
-__global__ __launch_bounds__(chol_threads<NT>())
-__attribute__((amdgpu_waves_per_eu(NT <= 8 ? 2 : 1))) void k_fac_diag(Tab tab)
+// Two work-groups per CU for blocks up to 128 (two waves per SIMD).  W
+// compute waves (the default, CholWaves) or, on levels with fewer interiors
+// than CUs, kWideWaves: one work-group per CU then, and the trailing updates
+// of every panel spread over 15 waves (three register tiles each for a
+// 128-row block) instead of three; the pivot chain is the same.
+constexpr int kWideWaves = 15;
+
+template <typename C, typename In, int NT, int W, typename Tab>
+__global__ __launch_bounds__(64 * (W + 1))
+__attribute__((amdgpu_waves_per_eu(NT <= 8 && W <= 3 ? 2 : 1))) void k_fac_diag(Tab tab)
 {
     using T = typename Stor<C>::type;
     __shared__ CholSmem<T, NT> sm;
@@ -165,7 +172,7 @@ __attribute__((amdgpu_waves_per_eu(NT <= 8 ? 2 : 1))) void k_fac_diag(Tab tab)
     const int np = s.np;
     const int64_t nn = (int64_t)np * np;
     const int64_t i = 2 * e + 1;
-    const int bad = chol_inv_block<C, NT, CholWaves<NT>::value, In>(s.Ad + i * nn, s.Li + e * nn, np, np, np, sm);
+    const int bad = chol_inv_block<C, NT, W, In>(s.Ad + i * nn, s.Li + e * nn, np, np, np, sm);
     if (bad >= 0 && threadIdx.x == 0)
         report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad);
 }
@@ -938,6 +945,19 @@ static inline unsigned grid_waves(int64_t units) { return (unsigned)((units + 3)
 
 // Register-tile bound NT (np = 16 nt, nt <= NT) of the block factorisation kernels.
 template <int NT> struct NtTag { static constexpr int value = NT; };
+// Compute units of the current device (cached per device).
+static int cu_count()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
 template <typename F> static hipError_t dispatch_nt(int np_max, F&& f)
 {
     const int nt = np_max / 16;
@@ -979,7 +999,15 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
         }
         return dispatch_nt(np, [&](auto nt) {
             constexpr int NT = decltype(nt)::value;
-            BDS_TIMED("fac_diag", st, k_fac_diag<C, In, NT><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(t));
+            if constexpr (NT == 8) {
+                if (td <= cu_count()) {
+                    BDS_TIMED("fac_diag", st,
+                              k_fac_diag<C, In, NT, kWideWaves><<<(unsigned)td, 64 * (kWideWaves + 1), 0, st>>>(t));
+                    return hipGetLastError();
+                }
+            }
+            BDS_TIMED("fac_diag", st,
+                      k_fac_diag<C, In, NT, CholWaves<NT>::value><<<(unsigned)td, chol_threads<NT>(), 0, st>>>(t));
             return hipGetLastError();
         });
     });
