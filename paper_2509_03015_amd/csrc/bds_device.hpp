@@ -84,7 +84,10 @@ __device__ __forceinline__ void acc_zero(typename AccT<T>::type (&acc)[RM][RN])
 // B_MASK: columns n >= ncols of B read as zero (right-hand sides with d < 16).
 // acc[a][b] accumulates the 16 x 16 output tile (m0 + 16a, n0 + 16b).
 // k0, k1: multiples of 16.
-template <typename T, int RM, int RN, bool A_MK, bool B_NK, bool B_MASK = false, typename SA,
+// UNR: k-steps whose loads are issued together before their products, so
+// that a wave has UNR steps in flight (launches too small to hide load
+// latency with other waves).
+template <typename T, int RM, int RN, bool A_MK, bool B_NK, bool B_MASK = false, int UNR = 1, typename SA,
           typename SB>
 __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], const SA* A,
                                          int64_t lda, const SB* B, int64_t ldb, int m0, int n0,
@@ -98,41 +101,15 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
     // step, so that each lane reads 32 contiguous bytes of A as an FP64 row does;
     // lane group g takes k = 8g .. 8g+7 of the 32, for A and B alike
     constexpr bool WIDE = std::is_same<T, double>::value && sizeof(SA) == 4 && A_MK;
-    if constexpr (WIDE) {
-        for (; kc + 32 <= k1; kc += 32) {
-            const int k = kc + 8 * g;
-            V a[RM][8], b[RN][8];
-#pragma unroll
-            for (int ta = 0; ta < RM; ++ta) {
-                const int m = m0 + 16 * ta + i;
-#pragma unroll
-                for (int s = 0; s < 8; ++s) a[ta][s] = (V)A[(int64_t)m * lda + k + s];
-            }
-#pragma unroll
-            for (int tb = 0; tb < RN; ++tb) {
-                const int n = n0 + 16 * tb + i;
-                const bool ok = !B_MASK || n < ncols;
-#pragma unroll
-                for (int s = 0; s < 8; ++s)
-                    b[tb][s] = ok ? (B_NK ? (V)B[(int64_t)n * ldb + k + s] : (V)B[(int64_t)(k + s) * ldb + n])
-                                  : (V)0;
-            }
-#pragma unroll
-            for (int s = 0; s < 8; ++s)
-#pragma unroll
-                for (int ta = 0; ta < RM; ++ta)
-#pragma unroll
-                    for (int tb = 0; tb < RN; ++tb) acc[ta][tb] = mma(a[ta][s], b[tb][s], acc[ta][tb]);
-        }
-    }
-    for (; kc < k1; kc += 16) {
-        const int k = kc + 4 * g;
-        V a[RM][4], b[RN][4];
+    constexpr int KS = WIDE ? 8 : 4;  // k per lane and step
+    // operands of one step at kc (lane group g: k = kc + KS g ..)
+    auto load = [&](int kc_, V (&a)[RM][KS], V (&b)[RN][KS]) {
+        const int k = kc_ + KS * g;
 #pragma unroll
         for (int ta = 0; ta < RM; ++ta) {
             const int m = m0 + 16 * ta + i;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < KS; ++s)
                 a[ta][s] = A_MK ? (V)A[(int64_t)m * lda + k + s] : (V)A[(int64_t)(k + s) * lda + m];
         }
 #pragma unroll
@@ -140,10 +117,12 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
             const int n = n0 + 16 * tb + i;
             const bool ok = !B_MASK || n < ncols;
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < KS; ++s)
                 b[tb][s] = ok ? (B_NK ? (V)B[(int64_t)n * ldb + k + s] : (V)B[(int64_t)(k + s) * ldb + n])
                               : (V)0;
         }
+    };
+    auto multiply = [&](const V (&a)[RM][KS], const V (&b)[RN][KS]) {
         if constexpr (std::is_same<T, bf16x>::value) {
             // one 16x16x16 instruction covers the four k-steps: lane (i, g) supplies k = 4g .. 4g+3
             sx4 ab[RM], bb[RN];
@@ -161,6 +140,50 @@ __device__ __forceinline__ void wave_mma(typename AccT<T>::type (&acc)[RM][RN], 
                 for (int tb = 0; tb < RN; ++tb)
                     acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ab[ta], bb[tb], acc[ta][tb], 0, 0, 0);
         } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int ta = 0; ta < RM; ++ta)
+#pragma unroll
+                    for (int tb = 0; tb < RN; ++tb) acc[ta][tb] = mma(a[ta][s], b[tb][s], acc[ta][tb]);
+        }
+    };
+    constexpr int KSTEP = 4 * KS;  // k per step: 16, or 32 on the WIDE path
+    if constexpr (UNR > 1) {
+        // UNR steps' loads first, then their products
+        for (; kc + UNR * KSTEP <= k1; kc += UNR * KSTEP) {
+            V a[UNR][RM][KS], b[UNR][RN][KS];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) load(kc + u * KSTEP, a[u], b[u]);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) multiply(a[u], b[u]);
+        }
+    }
+    for (; kc + KSTEP <= k1; kc += KSTEP) {
+        V a[RM][KS], b[RN][KS];
+        load(kc, a, b);
+        multiply(a, b);
+    }
+    if constexpr (WIDE) {
+        // a last 16 k in 16-k steps (k1 - k0 is a multiple of 16)
+        for (; kc < k1; kc += 16) {
+            const int k = kc + 4 * g;
+            V a[RM][4], b[RN][4];
+#pragma unroll
+            for (int ta = 0; ta < RM; ++ta) {
+                const int m = m0 + 16 * ta + i;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a[ta][s] = (V)A[(int64_t)m * lda + k + s];
+            }
+#pragma unroll
+            for (int tb = 0; tb < RN; ++tb) {
+                const int n = n0 + 16 * tb + i;
+                const bool ok = !B_MASK || n < ncols;
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    b[tb][s] = ok ? (B_NK ? (V)B[(int64_t)n * ldb + k + s] : (V)B[(int64_t)(k + s) * ldb + n])
+                                  : (V)0;
+            }
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll

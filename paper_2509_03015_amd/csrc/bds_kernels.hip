@@ -521,7 +521,7 @@ __global__ __launch_bounds__(chol_threads<NT>()) void k_coarse_factor(Tab tab)
 // ---------------------------------------------------------------------------
 // solve (vectors in FP64; factor blocks of type T converted on load)
 
-template <typename T, int R, typename Tab>
+template <typename T, int R, int U, typename Tab>
 __global__ __launch_bounds__(256) void k_sol_fwd_int(Tab tab)
 {
     using A = typename AccT<double>::type;
@@ -537,15 +537,15 @@ __global__ __launch_bounds__(256) void k_sol_fwd_int(Tab tab)
     const int64_t i = 2 * e + 1;
     A acc[R][1];
     acc_zero<double, R, 1>(acc);
-    wave_mma<double, R, 1, true, false, true>(acc, s.Li + e * nn + (int64_t)m0 * np, np, s.B + i * nd + c0, d,
-                                              0, 0, 0, min(np, m0 + 16 * R), d - c0);
+    wave_mma<double, R, 1, true, false, true, U>(acc, s.Li + e * nn + (int64_t)m0 * np, np, s.B + i * nd + c0, d,
+                                                 0, 0, 0, min(np, m0 + 16 * R), d - c0);
     double* y = s.Y + e * nd;
     acc_foreach<double, R, 1>(acc, m0, c0, [&](int m, int n, double v) {
         if (n < d) y[(int64_t)m * d + n] = v;
     });
 }
 
-template <typename T, int R, typename Tab>
+template <typename T, int R, int U, typename Tab>
 __global__ __launch_bounds__(256) void k_sol_fwd_sep(Tab tab)
 {
     using A = typename AccT<double>::type;
@@ -561,11 +561,11 @@ __global__ __launch_bounds__(256) void k_sol_fwd_sep(Tab tab)
     A acc[R][1];
     acc_zero<double, R, 1>(acc);
     if (j >= 1)
-        wave_mma<double, R, 1, true, false, true>(acc, s.Pr + (j - 1) * nn + (int64_t)m0 * np, np,
-                                                  s.Y + (j - 1) * nd + c0, d, 0, 0, 0, np, d - c0);
+        wave_mma<double, R, 1, true, false, true, U>(acc, s.Pr + (j - 1) * nn + (int64_t)m0 * np, np,
+                                                     s.Y + (j - 1) * nd + c0, d, 0, 0, 0, np, d - c0);
     if (2 * j + 1 < s.M)
-        wave_mma<double, R, 1, true, false, true>(acc, s.Wt + j * nn + (int64_t)m0 * np, np, s.Y + j * nd + c0, d,
-                                                  0, 0, 0, np, d - c0);
+        wave_mma<double, R, 1, true, false, true, U>(acc, s.Wt + j * nn + (int64_t)m0 * np, np,
+                                                     s.Y + j * nd + c0, d, 0, 0, 0, np, d - c0);
     const double* b = s.B + 2 * j * nd;
     double* out = s.Bn + j * nd;
     acc_foreach<double, R, 1>(acc, m0, c0, [&](int m, int n, double v) {
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256) void k_sol_fwd_sep(Tab tab)
 
 // One work-group of min(4, np / 16R) waves per (interior, 16 columns); the
 // launch provides np * 16 doubles of dynamic LDS for the corrected right-hand side.
-template <typename T, int R, typename Tab>
+template <typename T, int R, int U, typename Tab>
 __global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
 {
     using A = typename AccT<double>::type;
@@ -595,11 +595,11 @@ __global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
         const int m0 = 16 * R * t;
         A acc[R][1];
         acc_zero<double, R, 1>(acc);
-        wave_mma<double, R, 1, false, false, true>(acc, s.Wt + e * nn + m0, np, s.Xn + e * nd + c0, d, 0, 0, 0,
-                                                   np, d - c0);
+        wave_mma<double, R, 1, false, false, true, U>(acc, s.Wt + e * nn + m0, np, s.Xn + e * nd + c0, d, 0, 0,
+                                                      0, np, d - c0);
         if (i + 1 < s.M)
-            wave_mma<double, R, 1, false, false, true>(acc, s.Pr + e * nn + m0, np, s.Xn + (e + 1) * nd + c0, d,
-                                                       0, 0, 0, np, d - c0);
+            wave_mma<double, R, 1, false, false, true, U>(acc, s.Pr + e * nn + m0, np, s.Xn + (e + 1) * nd + c0,
+                                                          d, 0, 0, 0, np, d - c0);
         const double* y = s.Y + e * nd;
         acc_foreach<double, R, 1>(acc, m0, 0, [&](int m, int n, double v) {
             tsm[m * 16 + n] = (c0 + n < d) ? y[(int64_t)m * d + c0 + n] - v : 0.0;
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
         A acc[R][1];
         acc_zero<double, R, 1>(acc);
         // Li^T is upper triangular: k >= m0
-        wave_mma<double, R, 1, false, false>(acc, s.Li + e * nn + m0, np, tsm, 16, 0, 0, m0, np);
+        wave_mma<double, R, 1, false, false, false, U>(acc, s.Li + e * nn + m0, np, tsm, 16, 0, 0, m0, np);
         double* x = s.X + i * nd;
         acc_foreach<double, R, 1>(acc, m0, c0, [&](int m, int n, double v) {
             if (n < d) x[(int64_t)m * d + n] = v;
@@ -1073,20 +1073,33 @@ hipError_t launch_coarse_factor(const CoarseFac<In>& one, const CoarseFac<In>* t
     });
 }
 
+// Solve launches with at most one work-group per CU cannot hide the latency
+// of a wave's k-steps behind other waves: their kernels unroll the k loop
+// (kSolveUnroll steps in flight per wave) instead.
+constexpr int kSolveUnroll = 4;
+
 template <typename T>
 hipError_t launch_solve_fwd(const SolLv<T>& one, const SolLv<T>* tab, const int64_t* si, const int64_t* ss,
                             int K, int64_t ti, int64_t ts, int np, const Tiling& tl, hipStream_t st)
 {
     const bool r2 = tl.sol == BDS_TILE_W32;
     hipError_t e = with_table(one, tab, si, K, ti, [&](auto t) {
-        if (r2) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2><<<grid_waves(ti), 256, 0, st>>>(t));
-        else BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1><<<grid_waves(ti), 256, 0, st>>>(t));
+        const unsigned g = grid_waves(ti);
+        const bool few = g <= (unsigned)cu_count();
+        if (r2 && few) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2, kSolveUnroll><<<g, 256, 0, st>>>(t));
+        else if (r2) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 2, 1><<<g, 256, 0, st>>>(t));
+        else if (few) BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1, kSolveUnroll><<<g, 256, 0, st>>>(t));
+        else BDS_TIMED("sol_fwd_int", st, k_sol_fwd_int<T, 1, 1><<<g, 256, 0, st>>>(t));
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
     return with_table(one, tab, ss, K, ts, [&](auto t) {
-        if (r2) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 2><<<grid_waves(ts), 256, 0, st>>>(t));
-        else BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1><<<grid_waves(ts), 256, 0, st>>>(t));
+        const unsigned g = grid_waves(ts);
+        const bool few = g <= (unsigned)cu_count();
+        if (r2 && few) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 2, kSolveUnroll><<<g, 256, 0, st>>>(t));
+        else if (r2) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 2, 1><<<g, 256, 0, st>>>(t));
+        else if (few) BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1, kSolveUnroll><<<g, 256, 0, st>>>(t));
+        else BDS_TIMED("sol_fwd_sep", st, k_sol_fwd_sep<T, 1, 1><<<g, 256, 0, st>>>(t));
         return hipGetLastError();
     });
 }
@@ -1101,8 +1114,12 @@ hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab, const int6
     const unsigned threads = 64u * (unsigned)std::min(4, np / (16 * R));
     const size_t lds = (size_t)np * 16 * sizeof(double);
     return with_table(one, tab, sb, K, tb, [&](auto t) {
-        if (R == 2) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2><<<(unsigned)tb, threads, lds, st>>>(t));
-        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1><<<(unsigned)tb, threads, lds, st>>>(t));
+        const bool few = tb <= cu_count();
+        const unsigned g = (unsigned)tb;
+        if (R == 2 && few) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2, kSolveUnroll><<<g, threads, lds, st>>>(t));
+        else if (R == 2) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2, 1><<<g, threads, lds, st>>>(t));
+        else if (few) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1, kSolveUnroll><<<g, threads, lds, st>>>(t));
+        else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1, 1><<<g, threads, lds, st>>>(t));
         return hipGetLastError();
     });
 }
