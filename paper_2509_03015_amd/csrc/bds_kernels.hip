@@ -152,7 +152,8 @@ int64_t units_resid(int N, int np, int d) { return (int64_t)N * (np / (16 * tile
 // ---------------------------------------------------------------------------
 // factorisation
 
-// Two work-groups per CU for blocks up to 128 (two waves per SIMD).  W
+// Four work-groups per CU for blocks up to 64 rows, two up to 128 (four or two
+// waves per SIMD).  W
 // compute waves (the default, CholWaves) or, on levels with fewer interiors
 // than CUs, kWideWaves: one work-group per CU then, and the trailing updates
 // of every panel spread over 15 waves (three register tiles each for a
@@ -161,7 +162,7 @@ constexpr int kWideWaves = 15;
 
 template <typename C, typename In, int NT, int W, typename Tab>
 __global__ __launch_bounds__(64 * (W + 1))
-__attribute__((amdgpu_waves_per_eu(NT <= 8 && W <= 3 ? 2 : 1))) void k_fac_diag(Tab tab)
+__attribute__((amdgpu_waves_per_eu(NT <= 4 && W <= 3 ? 4 : (NT <= 8 && W <= 3 ? 2 : 1)))) void k_fac_diag(Tab tab)
 {
     using T = typename Stor<C>::type;
     __shared__ CholSmem<T, NT> sm;
