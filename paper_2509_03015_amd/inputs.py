@@ -27,6 +27,14 @@ Generators
                 ``H_k ~ N(0,1)`` with m = n/2 rows, drawn per step.  ``rho``
                 sets the conditioning.
 ``gen_batched`` K independent systems of uneven size, each from ``gen_dd``.
+``gen_kalman_neuro``  the smoothing problem of the paper's neuroscience example
+                (Sec. 4.2): a latent state of dimension n driven by damped
+                two-dimensional rotations, observed through a tall
+                well-conditioned H (m rows) with diagonal measurement noise R
+                larger than the dense SPD process noise Q, over N steps; the
+                right-hand side is the measurement one, ``b = H^T R^-1 z +
+                G^T Q^-1 zeta`` (not manufactured), so the exact X is the MAP
+                trajectory, which a Rauch-Tung-Striebel smoother also gives.
 """
 from __future__ import annotations
 
@@ -118,3 +126,83 @@ def gen_batched(K: int = 512, seed: int = 0, **size_kw):
     for k, (N, n, d) in enumerate(batched_sizes(K, seed, **size_kw)):
         out.append(gen_dd(N, n, d, seed=seed * 100003 + k + 1))
     return out
+
+
+def kalman_neuro_model(N: int = 100, n: int = 256, m: int = 1024, seed: int = 0, dt: float = 0.1):
+    """Model and simulated data of the neuroscience-style smoothing example.
+
+    The paper fixes n, m, N and dt and describes the matrices only in words; the
+    parameters below are this generator's reading:
+
+    * ``G = U diag(lam_i R(theta_i)) U^T``: n/2 damped 2 x 2 rotations in a
+      Haar-random basis, decay ``lam_i = exp(-dt / tau_i)`` with tau_i ~ U(0.5, 2) s
+      and ``theta_i = 2 pi f_i dt`` with f_i ~ U(0.5, 2) Hz (slow rotational
+      dynamics); ``G_1 = I`` (the known initial state enters through zeta);
+    * ``Q = q (0.5 I + V V^T / n)`` with V ~ N(0, 1) (dense SPD), q = 0.01;
+    * ``R = diag(r_j)`` with r_j = 10 q U(0.5, 1.5) (measurements less reliable
+      than the dynamics);
+    * ``H ~ N(0, 1) / sqrt(m)`` (m x n, condition number about
+      (1 + sqrt(n/m)) / (1 - sqrt(n/m)) = 3 for m = 4n);
+    * x_0 ~ N(0, I) known; x_k = G_k x_{k-1} + w_k, z_k = H x_k + v_k with
+      w_k ~ N(0, Q), v_k ~ N(0, R).
+
+    Returns a dict with G, Q, r (the diagonal of R), H, x0, the simulated states
+    x (N, n) and measurements z (N, m).  Draw order: U, tau, f, V, r, H, x0, w, v.
+    """
+    if n % 2:
+        raise ValueError("n must be even (pairs of rotating coordinates)")
+    rng = np.random.default_rng(seed)
+    U = haar_orthogonal(rng, n)
+    tau = rng.uniform(0.5, 2.0, n // 2)
+    f = rng.uniform(0.5, 2.0, n // 2)
+    lam = np.exp(-dt / tau)
+    th = 2.0 * np.pi * f * dt
+    D = np.zeros((n, n))
+    for i in range(n // 2):
+        c, s_ = np.cos(th[i]), np.sin(th[i])
+        D[2 * i:2 * i + 2, 2 * i:2 * i + 2] = lam[i] * np.array([[c, -s_], [s_, c]])
+    G = U @ D @ U.T
+    q = 0.01
+    V = rng.standard_normal((n, n))
+    Q = q * (0.5 * np.eye(n) + V @ V.T / n)
+    Q = 0.5 * (Q + Q.T)
+    r = 10.0 * q * rng.uniform(0.5, 1.5, m)
+    H = rng.standard_normal((m, n)) / np.sqrt(m)
+    x0 = rng.standard_normal(n)
+    Lq = np.linalg.cholesky(Q)
+    w = rng.standard_normal((N, n)) @ Lq.T
+    v = rng.standard_normal((N, m)) * np.sqrt(r)[None, :]
+    x = np.empty((N, n))
+    prev = x0
+    for k in range(N):
+        prev = (prev if k == 0 else G @ prev) + w[k]
+        x[k] = prev
+    z = x @ H.T + v
+    return {"G": G, "Q": Q, "r": r, "H": H, "x0": x0, "x": x, "z": z}
+
+
+def gen_kalman_neuro(N: int = 100, n: int = 256, m: int = 1024, seed: int = 0):
+    """The MAP normal equations of ``kalman_neuro_model`` as a block-tridiagonal system.
+
+    Blocks as the paper writes them (Sec. 4.2), with G_1 = I, G_{N+1} = 0 and
+    time-invariant G, Q, H, R otherwise:
+    ``A[k,k] = Q^-1 + G^T Q^-1 G (k < N) + H^T R^-1 H``, ``A[k+1,k] = -Q^-1 G``;
+    ``b_k = H^T R^-1 z_k``, plus ``Q^-1 x_0`` in the first block (the term
+    ``G^T Q^-1 zeta`` with zeta = (G_1 x_0, 0, ..., 0)).  Returns
+    ``(Ad, As, x, B, model)``: x is the simulated trajectory (not the solution),
+    B has shape (N, n, 1).
+    """
+    mdl = kalman_neuro_model(N, n, m, seed)
+    G, Q, r, H = mdl["G"], mdl["Q"], mdl["r"], mdl["H"]
+    Qi = np.linalg.inv(Q)
+    Qi = 0.5 * (Qi + Qi.T)
+    HtRiH = H.T @ (H / r[:, None])
+    Ad = np.broadcast_to(Qi + HtRiH, (N, n, n)).copy()
+    if N > 1:
+        Ad[:-1] += G.T @ Qi @ G
+    Ad = 0.5 * (Ad + np.transpose(Ad, (0, 2, 1)))
+    As = np.broadcast_to(-Qi @ G, (max(N - 1, 0), n, n)).copy()
+    B = ((mdl["z"] / r[None, :]) @ H)[:, :, None].copy()
+    B[0, :, 0] += Qi @ mdl["x0"]
+    return Ad, As, mdl["x"][:, :, None].copy(), B, mdl
+
