@@ -194,9 +194,9 @@ __attribute__((amdgpu_waves_per_eu(NT <= 4 && W <= 3 ? 4 : (NT <= 8 && W <= 3 ? 
 // every launch, so each launch takes the level's interior table unchanged.
 constexpr int kHalf = 128;
 
-template <typename C, typename In, bool SECOND, typename Tab>
-__global__ __launch_bounds__(chol_threads<8>())
-__attribute__((amdgpu_waves_per_eu(2))) void k_fac_diag_half(Tab tab)
+template <typename C, typename In, bool SECOND, int W, typename Tab>
+__global__ __launch_bounds__(64 * (W + 1))
+__attribute__((amdgpu_waves_per_eu(W <= 3 ? 2 : 1))) void k_fac_diag_half(Tab tab)
 {
     using T = typename Stor<C>::type;
     __shared__ CholSmem<T, 8> sm;
@@ -210,10 +210,9 @@ __attribute__((amdgpu_waves_per_eu(2))) void k_fac_diag_half(Tab tab)
     T* Li = s.Li + e * nn;
     int bad;
     if constexpr (!SECOND)
-        bad = chol_inv_block<C, 8, CholWaves<8>::value, In>(s.Ad + i * nn, Li, kHalf, np, np, sm);
+        bad = chol_inv_block<C, 8, W, In>(s.Ad + i * nn, Li, kHalf, np, np, sm);
     else
-        bad = chol_inv_block<C, 8, CholWaves<8>::value, T>(Li + kHalf, Li + (int64_t)kHalf * np + kHalf, kHalf, np,
-                                                            np, sm);
+        bad = chol_inv_block<C, 8, W, T>(Li + kHalf, Li + (int64_t)kHalf * np + kHalf, kHalf, np, np, sm);
     if (bad >= 0 && threadIdx.x == 0)
         report_notspd(s.info, s.level, (int)i, (int)(i << s.level), bad + (SECOND ? kHalf : 0));
 }
@@ -989,11 +988,15 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
             // 2 x 2 recursion over 128-row halves (see k_fac_diag_half); FP64 only:
             // in FP32 the explicit 128-row inverses cost the refinement an
             // iteration at kappa ~ 1e6, which the 16-row pivot inverses do not
-            const unsigned nb = (unsigned)td, ct = chol_threads<8>();
-            BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false><<<nb, ct, 0, st>>>(t));
+            // halves on levels with no more interiors than CUs: 16-wave work-groups (see k_fac_diag)
+            const unsigned nb = (unsigned)td, ct = chol_threads<8>(), cw = 64 * (kWideWaves + 1);
+            const bool wide = td <= cu_count();
+            if (wide) BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false, kWideWaves><<<nb, cw, 0, st>>>(t));
+            else BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false, CholWaves<8>::value><<<nb, ct, 0, st>>>(t));
             BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 0><<<nb, 256, 0, st>>>(t));
             BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 1><<<nb, 256, 0, st>>>(t));
-            BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, true><<<nb, ct, 0, st>>>(t));
+            if (wide) BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, true, kWideWaves><<<nb, cw, 0, st>>>(t));
+            else BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, true, CholWaves<8>::value><<<nb, ct, 0, st>>>(t));
             BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 2><<<nb, 256, 0, st>>>(t));
             BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 3><<<nb, 256, 0, st>>>(t));
             return hipGetLastError();
