@@ -190,8 +190,10 @@ __attribute__((amdgpu_waves_per_eu(NT <= 4 && W <= 3 ? 4 : (NT <= 8 && W <= 3 ? 
 //   X21 = -L22^-1 T                     (step 3)
 // so that Li = [L11^-1 0; X21 L22^-1].  L21 is kept in Li's lower-left
 // quadrant until X21 replaces it; S and then T live in the upper-right
-// quadrant, which step 3 clears at the end.  One work-group per interior in
-// every launch, so each launch takes the level's interior table unchanged.
+// quadrant, which step 3 clears at the end.  Every launch takes the level's
+// interior table unchanged: the half factorisations run one work-group per
+// interior, the link products one per 64 x 64 macro tile (step 3: one per
+// column of macro tiles, the only reader of that column of T).
 constexpr int kHalf = 128;
 
 template <typename C, typename In, bool SECOND, int W, typename Tab>
@@ -223,8 +225,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     using T = typename Stor<C>::type;
     using Acc = typename AccT<C>::type;
     constexpr int MT = 64, KC = 16, R = MT / 32, H = kHalf, TP = H / MT;
+    // work-groups per interior: one per macro tile, or (step 3) one per column of
+    // macro tiles, so that each column of T has a single reader, which clears it
+    constexpr int PER = STEP == 3 ? TP : TP * TP;
     __shared__ GemmSmem<T, MT, KC> sm;
-    const int64_t u = blockIdx.x;
+    const int64_t w = xcd_local_index(blockIdx.x, gridDim.x);
+    const int64_t u = w / PER;
+    const int part = (int)(w % PER);
     if (u >= tab.total) return;
     int64_t e;
     const auto& s = tab.get(u, e);
@@ -237,9 +244,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     T* Low = Li + (int64_t)H * np;         // L21, then X21
     T* Scr = Li + H;                       // S, then T
     T* L22i = Li + (int64_t)H * np + H;    // L22^-1
-    for (int t = 0; t < TP * TP; ++t) {
-        const int tm = t / TP, tn = t % TP;
-        if (STEP == 1 && tn > tm) continue;  // S: lower macro tiles
+    for (int q = 0; q < (STEP == 3 ? TP : 1); ++q) {
+        const int tm = STEP == 3 ? q : part / TP, tn = STEP == 3 ? part : part % TP;
+        if (STEP == 1 && tn > tm) return;  // S: lower macro tiles
         const int m0 = MT * tm, n0 = MT * tn;
         Acc acc[R][R];
         acc_zero<C, R, R>(acc);
@@ -271,9 +278,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();  // the LDS buffers are reused by the next tile
     }
     if constexpr (STEP == 3) {
-        // every read of the scratch quadrant of this interior is done: clear it
-        for (int q = threadIdx.x; q < H * H; q += blockDim.x)
-            Scr[(int64_t)(q / H) * np + q % H] = (T)0;
+        // this work-group was the only reader of column block `part` of T: clear it
+        const int n0 = MT * part;
+        for (int q = threadIdx.x; q < H * MT; q += blockDim.x)
+            Scr[(int64_t)(q / MT) * np + n0 + q % MT] = (T)0;
     }
 }
 
@@ -993,12 +1001,12 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
             const bool wide = td <= cu_count();
             if (wide) BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false, kWideWaves><<<nb, cw, 0, st>>>(t));
             else BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, false, CholWaves<8>::value><<<nb, ct, 0, st>>>(t));
-            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 0><<<nb, 256, 0, st>>>(t));
-            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 1><<<nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 0><<<4 * nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 1><<<4 * nb, 256, 0, st>>>(t));
             if (wide) BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, true, kWideWaves><<<nb, cw, 0, st>>>(t));
             else BDS_TIMED("fac_diag", st, k_fac_diag_half<C, In, true, CholWaves<8>::value><<<nb, ct, 0, st>>>(t));
-            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 2><<<nb, 256, 0, st>>>(t));
-            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 3><<<nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 2><<<4 * nb, 256, 0, st>>>(t));
+            BDS_TIMED("fac_diag", st, k_fac_diag_link<C, In, 3><<<2 * nb, 256, 0, st>>>(t));
             return hipGetLastError();
         }
         return dispatch_nt(np, [&](auto nt) {
