@@ -581,10 +581,13 @@ __global__ __launch_bounds__(256) void k_sol_fwd_sep(Tab tab)
     });
 }
 
-// One work-group of min(4, np / 16R) waves per (interior, 16 columns); the
+// One work-group of min(4, np / 16R) waves per (interior, 16 columns); for
+// launches of at most one work-group per CU, the unrolled form with up to 4
+// waves (U = 4) or, where a block has more row tiles, 8 waves with two k-steps
+// in flight (U = 2, which fits the 256 registers per lane of 8 waves); the
 // launch provides np * 16 doubles of dynamic LDS for the corrected right-hand side.
 template <typename T, int R, int U, typename Tab>
-__global__ __launch_bounds__(256) void k_sol_bwd(Tab tab)
+__global__ __launch_bounds__(U == 2 ? 512 : 256) void k_sol_bwd(Tab tab)
 {
     using A = typename AccT<double>::type;
     extern __shared__ double tsm[];
@@ -1123,13 +1126,16 @@ hipError_t launch_solve_bwd(const SolLv<T>& one, const SolLv<T>* tab, const int6
     // a work-group's four waves share the np / (16 R) row tiles of one interior:
     // 32-row tiles only where that still leaves a tile per wave
     const int R = (tl.sol == BDS_TILE_W32 && np >= 128) ? 2 : 1;
-    const unsigned threads = 64u * (unsigned)std::min(4, np / (16 * R));
     const size_t lds = (size_t)np * 16 * sizeof(double);
     return with_table(one, tab, sb, K, tb, [&](auto t) {
         const bool few = tb <= cu_count();
+        const bool eight = few && np / (16 * R) > 4;
+        const unsigned threads = 64u * (unsigned)std::min(eight ? 8 : 4, np / (16 * R));
         const unsigned g = (unsigned)tb;
-        if (R == 2 && few) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2, kSolveUnroll><<<g, threads, lds, st>>>(t));
+        if (R == 2 && eight) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2, 2><<<g, threads, lds, st>>>(t));
+        else if (R == 2 && few) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2, kSolveUnroll><<<g, threads, lds, st>>>(t));
         else if (R == 2) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 2, 1><<<g, threads, lds, st>>>(t));
+        else if (eight) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1, 2><<<g, threads, lds, st>>>(t));
         else if (few) BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1, kSolveUnroll><<<g, threads, lds, st>>>(t));
         else BDS_TIMED("sol_bwd", st, k_sol_bwd<T, 1, 1><<<g, threads, lds, st>>>(t));
         return hipGetLastError();
