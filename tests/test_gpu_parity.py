@@ -169,3 +169,15 @@ def test_configs1_full_size_properties(S):
     # sampled blocks: the first 64 block rows equal the oracle's solve of the whole system
     # restricted there is not computable alone; compare against the oracle on a leading
     # subsystem is invalid, so sample via the residual instead (done above).
+
+
+@pytest.mark.parametrize("N,n,d,prec", [(1200, 128, 16, "f64"), (600, 256, 1, "f64"), (1100, 128, 2, "f32")])
+def test_levels_across_the_small_launch_forms(S, N, n, d, prec):
+    """Sizes whose top levels have more interiors than CUs and whose deeper levels have fewer, so that
+    one solve runs both launch forms of every kernel that has two (16-wave factor work-groups and
+    unrolled or 8-wave solve sweeps on small levels, the 256-row split with its per-tile link products)."""
+    _say("small-launch crossover", N, n, d, prec)
+    Ad, As, Xt, B = inputs.gen_dd(N, n, d, seed=N + n)
+    X, F = gpu_solve(S, Ad, As, B, prec=prec, **({"refine_tol": 1e-12} if prec != "f64" else {}))
+    assert F.info()["status"] == 0
+    assert relerr(X, oracle.solve(Ad, As, B)) <= (1e-12 if prec == "f64" else 1e-10)
