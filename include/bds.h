@@ -92,7 +92,9 @@ typedef struct bds_desc {
  * Tile shapes (bds_desc.tiles).  Each field selects how one step of a
  * reduction level is cut into work for the GPU; BDS_TILE_RULE leaves it to
  * the library's rule (a function of the padded block size np and the
- * precision), which is also what bds_tune starts from.
+ * precision; for the coupling and Schur fields of bds_factor also of the
+ * level: levels whose work-group tiles would launch no more work-groups than
+ * the device has CUs take W16), which is also what bds_tune starts from.
  *   couple: the coupling products of Alg. 4 (trsm as products with the
  *           stored inverse factor);
  *   schur:  the Schur updates of Alg. 3;
@@ -201,7 +203,10 @@ int bds_solve_batched(int64_t K, const bds_desc* descs, const void* factor_ws,
  * configurations and writes the fastest descriptor to *best (nstar and tiles
  * chosen; every other field copied from *desc).  Coordinate search from the
  * library's choices: nstar over {1, 2, 4, ..., 64} (up to N), then each tile
- * field over the shapes that fit np; each candidate is run once untimed and
+ * field the caller left at zero over the shapes that fit np, against zero
+ * itself (the library's choice, which for the coupling and Schur fields of a
+ * single system takes per-wave tiles on levels too small for work-group
+ * tiles); a field of *best stays zero where that wins.  Each candidate is run once untimed and
  * timed over `reps` runs (reps <= 0: 3) with HIP events on `stream`.  The
  * search excludes workspace sizing and is meant to run once per problem
  * shape, before the timed work (the paper's Init phase).

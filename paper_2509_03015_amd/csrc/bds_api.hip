@@ -43,6 +43,7 @@ SysPlan make_plan(const bds_desc& d, size_t base_f, size_t base_s)
     p.esize = matrix_elem_bytes(d.prec);
     p.packed = p.np != p.n;
     resolve_tiling((int)p.np, p.prec, d.tiles, p.tl);  // checked by check_desc
+    p.tiles_req = d.tiles;
     size_t f = base_f, s = base_s;
     auto take = [](size_t& off, size_t bytes) {
         const size_t o = off;
@@ -114,19 +115,20 @@ int factor_impl(const SysPlan& p, const double* Ad, const double* As, void* fws,
     for (size_t l = 0; l < p.lv.size(); ++l) {
         const LevelPlan& L = p.lv[l];
         const int M = (int)L.M;
+        const Tiling lt = level_tiling(p.tl, p.tiles_req, M, np);
         if (l == 0) {
             FacLv<T, double> r{a0.Ad, a0.As, at<T>(fws, L.Li), at<T>(fws, L.Wt), at<T>(fws, L.Pr),
                                at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, 0, 0, info};
             BDS_TRY(launch_factor_level<C, double>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                                   units_fac_couple(M, np, p.tl.couple),
-                                                   units_fac_schur(M, np, p.tl.schur), np, p.tl, st));
+                                                   units_fac_couple(M, np, lt.couple),
+                                                   units_fac_schur(M, np, lt.schur), np, lt, st));
         } else {
             const LevelPlan& P = p.lv[l - 1];
             FacLv<T, T> r{at<T>(fws, P.Adn), at<T>(fws, P.Asn), at<T>(fws, L.Li), at<T>(fws, L.Wt),
                           at<T>(fws, L.Pr), at<T>(fws, L.Adn), at<T>(fws, L.Asn), M, np, (int)l, 0, info};
             BDS_TRY(launch_factor_level<C, T>(r, nullptr, nullptr, nullptr, nullptr, 1, units_fac_diag(M),
-                                              units_fac_couple(M, np, p.tl.couple),
-                                              units_fac_schur(M, np, p.tl.schur), np, p.tl, st));
+                                              units_fac_couple(M, np, lt.couple),
+                                              units_fac_schur(M, np, lt.schur), np, lt, st));
         }
     }
     const int Lv = (int)p.lv.size();

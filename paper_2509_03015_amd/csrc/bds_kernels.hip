@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
-template <typename C, typename In, int R, typename Tab>
+template <typename C, typename In, int R, int U, typename Tab>
 __global__ __launch_bounds__(256) void k_fac_couple(Tab tab)
 {
     using T = typename Stor<C>::type;
@@ -306,21 +306,21 @@ __global__ __launch_bounds__(256) void k_fac_couple(Tab tab)
     acc_zero<C, R, R>(acc);
     if (which == 0) {
         // Wt = A[i,i-1]^T Li^T; Li^T upper: k < n0 + 16R
-        wave_mma<C, R, R, false, true>(acc, s.As + (i - 1) * nn + m0, np, Li + (int64_t)n0 * np, np, 0, 0, 0,
-                                       min(np, n0 + 16 * R));
+        wave_mma<C, R, R, false, true, false, U>(acc, s.As + (i - 1) * nn + m0, np, Li + (int64_t)n0 * np, np, 0,
+                                                 0, 0, min(np, n0 + 16 * R));
         T* out = s.Wt + e * nn;
         acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
     } else {
         if (i + 1 >= s.M) return;
         // Pr = A[i+1,i] * Li^T; Li^T upper: k < n0 + 16R
-        wave_mma<C, R, R, true, true>(acc, s.As + i * nn + (int64_t)m0 * np, np, Li + (int64_t)n0 * np, np,
-                                      0, 0, 0, min(np, n0 + 16 * R));
+        wave_mma<C, R, R, true, true, false, U>(acc, s.As + i * nn + (int64_t)m0 * np, np, Li + (int64_t)n0 * np,
+                                                np, 0, 0, 0, min(np, n0 + 16 * R));
         T* out = s.Pr + e * nn;
         acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = v; });
     }
 }
 
-template <typename C, typename In, int R, typename Tab>
+template <typename C, typename In, int R, int U, typename Tab>
 __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
 {
     using T = typename Stor<C>::type;
@@ -345,11 +345,13 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
         const int m0 = 16 * R * tm, n0 = 16 * R * tn;
         if (j >= 1) {
             const T* P = s.Pr + (j - 1) * nn;
-            wave_mma<C, R, R, true, true>(acc, P + (int64_t)m0 * np, np, P + (int64_t)n0 * np, np, 0, 0, 0, np);
+            wave_mma<C, R, R, true, true, false, U>(acc, P + (int64_t)m0 * np, np, P + (int64_t)n0 * np, np, 0, 0, 0,
+                                                    np);
         }
         if (2 * j + 1 < s.M) {
             const T* W = s.Wt + j * nn;
-            wave_mma<C, R, R, true, true>(acc, W + (int64_t)m0 * np, np, W + (int64_t)n0 * np, np, 0, 0, 0, np);
+            wave_mma<C, R, R, true, true, false, U>(acc, W + (int64_t)m0 * np, np, W + (int64_t)n0 * np, np, 0, 0, 0,
+                                                    np);
         }
         const In* a = s.Ad + 2 * j * nn;
         T* out = s.Adn + j * nn;
@@ -362,7 +364,8 @@ __global__ __launch_bounds__(256) void k_fac_schur(Tab tab)
         const int m0 = 16 * R * (t / tp), n0 = 16 * R * (t % tp);
         const T* P = s.Pr + j * nn;
         const T* W = s.Wt + j * nn;
-        wave_mma<C, R, R, true, true>(acc, P + (int64_t)m0 * np, np, W + (int64_t)n0 * np, np, 0, 0, 0, np);
+        wave_mma<C, R, R, true, true, false, U>(acc, P + (int64_t)m0 * np, np, W + (int64_t)n0 * np, np, 0, 0, 0,
+                                                np);
         T* out = s.Asn + j * nn;
         acc_foreach<C, R, R>(acc, m0, n0, [&](int m, int n, T v) { out[(int64_t)m * np + n] = -v; });
     }
@@ -969,6 +972,16 @@ static int cu_count()
     return n;
 }
 
+Tiling level_tiling(const Tiling& tl, int32_t req, int M, int np)
+{
+    Tiling t = tl;
+    const int64_t few = cu_count();
+    if (!(req & 15) && t.couple >= BDS_TILE_G64 && units_fac_couple(M, np, t.couple) <= few) t.couple = BDS_TILE_W16;
+    if (!((req >> 4) & 15) && t.schur >= BDS_TILE_G64 && units_fac_schur(M, np, t.schur) <= few)
+        t.schur = BDS_TILE_W16;
+    return t;
+}
+
 template <typename F> static hipError_t dispatch_nt(int np_max, F&& f)
 {
     const int nt = np_max / 16;
@@ -1030,6 +1043,9 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
     // chunk depth of the work-group products: 32 for FP32 products on blocks of 128
     // and more (measured faster there; 16 is faster for 64-wide blocks and BF16)
     const bool deep = std::is_same<C, float>::value && np >= 128;
+    // per-wave tile products in launches of at most one work-group per CU: four
+    // k-steps of loads in flight per wave (see launch_solve_fwd)
+    const unsigned few = (unsigned)cu_count();
     e = with_table(one, tab, sc, K, tc, [&](auto t) {
         switch (tl.couple) {
         case BDS_TILE_G128:
@@ -1040,8 +1056,14 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
             if (deep) BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64, 32><<<(unsigned)tc, 256, 0, st>>>(t));
             else BDS_TIMED("fac_couple", st, k_fac_couple_wg<C, In, 64, 16><<<(unsigned)tc, 256, 0, st>>>(t));
             break;
-        case BDS_TILE_W32: BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2><<<grid_waves(tc), 256, 0, st>>>(t)); break;
-        default: BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1><<<grid_waves(tc), 256, 0, st>>>(t)); break;
+        case BDS_TILE_W32:
+            if (grid_waves(tc) <= few) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2, 4><<<grid_waves(tc), 256, 0, st>>>(t));
+            else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 2, 1><<<grid_waves(tc), 256, 0, st>>>(t));
+            break;
+        default:
+            if (grid_waves(tc) <= few) BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1, 4><<<grid_waves(tc), 256, 0, st>>>(t));
+            else BDS_TIMED("fac_couple", st, k_fac_couple<C, In, 1, 1><<<grid_waves(tc), 256, 0, st>>>(t));
+            break;
         }
         return hipGetLastError();
     });
@@ -1056,8 +1078,14 @@ hipError_t launch_factor_level(const FacLv<typename Stor<C>::type, In>& one,
             if (deep) BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64, 32><<<(unsigned)ts, 256, 0, st>>>(t));
             else BDS_TIMED("fac_schur", st, k_fac_schur_wg<C, In, 64, 16><<<(unsigned)ts, 256, 0, st>>>(t));
             break;
-        case BDS_TILE_W32: BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2><<<grid_waves(ts), 256, 0, st>>>(t)); break;
-        default: BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1><<<grid_waves(ts), 256, 0, st>>>(t)); break;
+        case BDS_TILE_W32:
+            if (grid_waves(ts) <= few) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2, 4><<<grid_waves(ts), 256, 0, st>>>(t));
+            else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 2, 1><<<grid_waves(ts), 256, 0, st>>>(t));
+            break;
+        default:
+            if (grid_waves(ts) <= few) BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1, 4><<<grid_waves(ts), 256, 0, st>>>(t));
+            else BDS_TIMED("fac_schur", st, k_fac_schur<C, In, 1, 1><<<grid_waves(ts), 256, 0, st>>>(t));
+            break;
         }
         return hipGetLastError();
     });

@@ -112,6 +112,11 @@ struct Tiling {
 bool resolve_tiling(int np, int prec, int32_t tiles, Tiling& out);
 // Tile codes that fit np for one field (couple/schur: all; solve: wave tiles).
 std::vector<int> tile_choices(int np, bool solve);
+// Tiling of one reduction level of M blocks: tl, except that the coupling and
+// Schur fields the caller left to the library (zero in req) take per-wave
+// 16 x 16 tiles on levels where the work-group tiles would launch no more
+// work-groups than the device has CUs.
+Tiling level_tiling(const Tiling& tl, int32_t req, int M, int np);
 
 // Work-unit counts per record (waves for wave kernels, work-groups otherwise).
 // tile_r(np) is the wave tile factor (a wave computes (16R) x (16R) outputs)

@@ -62,6 +62,7 @@ struct SysPlan {
     double refine_tol = kDefaultRefineTol;
     size_t esize = 8;
     Tiling tl;            // tile shapes of the reduction levels
+    int32_t tiles_req = 0;  // the caller's tile field (0 in a field: left to the library)
     bool packed = false;  // n % 16 != 0: user arrays are copied into padded buffers
     std::vector<LevelPlan> lv;
     int64_t Mc = 0;       // blocks of the coarse system

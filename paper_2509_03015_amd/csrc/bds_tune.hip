@@ -123,9 +123,10 @@ int bds_tune(const bds_desc* desc, const double* Ad, const double* As, const dou
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int np = (int)round_up(desc->n, 16);
 
+    // tile fields start at the caller's value: a zero (library choice, which may
+    // differ per level) competes with the explicit codes and is kept if it wins
     bds_desc cur = *desc;
     cur.nstar = nstar_candidates(*desc)[0];
-    cur.tiles = explicit_tiles(*desc);
     auto run_one = [&](const bds_desc& d) {
         return std::function<int()>([&, d] {
             int r = bds_factor(&d, Ad, As, factor_ws, factor_bytes, info, st);
@@ -170,7 +171,6 @@ int bds_tune(const bds_desc* desc, const double* Ad, const double* As, const dou
         cur = winner;
         for (int code : tile_choices(np, f == 2)) {
             if (stop) break;
-            if (code == field(cur.tiles, f)) continue;
             bds_desc c = cur;
             c.tiles = with_field(cur.tiles, f, code);
             rc = consider(c);

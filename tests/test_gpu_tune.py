@@ -95,7 +95,8 @@ def test_tune_picks_a_valid_configuration(S, N, n, d, prec):
     F = S.factor(dev(Ad), dev(As), prec=prec)
     choice = F.tune(B_t, reps=2)
     assert choice["nstar"] >= 1 and choice["nstar"] <= max(64, 1)
-    assert all(choice[k] != "rule" for k in ("couple", "schur", "solve"))
+    # "rule" (the library's choice, which may differ per level) competes with the explicit codes
+    assert all(choice[k] in ("rule", "w16", "w32", "g64", "g128") for k in ("couple", "schur", "solve"))
     X = F.solve(B_t).cpu().numpy()
     assert relerr(X, oracle.solve(Ad, As, B)) <= 1e-12
     # the tuned factor keeps working for another right-hand side
