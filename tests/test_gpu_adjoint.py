@@ -56,9 +56,9 @@ def test_backward_matches_oracle_adjoint(S, N, n, d):
         assert relerr(dAs, rAs) <= 1e-12
 
 
-def test_configs4_adjoint_against_oracle_and_fd(S):
+def test_adjoint_N4096_n32_d4_against_oracle_and_fd(S):
     """N=4096, n=32, d=4, Kalman Hessian at kappa ~ 1e4: 64 random entries by central differences."""
-    _say("configs4 adjoint")
+    _say("adjoint N=4096 n=32 d=4")
     N, n, d = 4096, 32, 4
     rho = inputs.KALMAN_RHO[n][1e4]
     Ad, As, _, B = inputs.gen_kalman(N, n, d, rho, seed=0)

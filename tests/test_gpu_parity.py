@@ -40,8 +40,8 @@ def gpu_solve(S, Ad, As, B, prec="f64", nstar=0, **kw):
     return X.cpu().numpy(), F
 
 
-def test_configs0_fp64_matches_oracle(S):
-    _say("configs0 N=64 n=16 d=1")
+def test_fp64_N64_n16_d1_matches_oracle(S):
+    _say("fp64 N=64 n=16 d=1")
     Ad, As, Xt, B = inputs.gen_dd(64, 16, 1, seed=0)
     X, F = gpu_solve(S, Ad, As, B)
     assert F.info()["status"] == 0
@@ -156,9 +156,9 @@ def test_nan_input_is_reported(S):
 
 
 @pytest.mark.slow
-def test_configs1_full_size_properties(S):
+def test_fp64_N16384_n128_d16_full_size_properties(S):
     """N=16384, n=128, d=16 (the benchmark configuration): manufactured solution and backward error."""
-    _say("configs1 full size")
+    _say("fp64 N=16384 n=128 d=16 full size")
     Ad, As, Xt, B = inputs.gen_dd(16384, 128, 16, seed=0)
     X, F = gpu_solve(S, Ad, As, B)
     assert F.info()["status"] == 0

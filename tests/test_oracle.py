@@ -124,7 +124,7 @@ def test_two_block_explicit_formula():
     assert relerr(X, np.stack([x0, x1])) < 1e-14
 
 
-def test_manufactured_solution_configs0():
+def test_manufactured_solution_N64_n16_d1():
     """N=64, n=16, d=1, diagonally dominant: X recovered to about kappa * u."""
     Ad, As, Xt, B = inputs.gen_dd(64, 16, 1, seed=0)
     assert relerr(oracle.solve(Ad, As, B), Xt) < 1e-14
